@@ -1,0 +1,234 @@
+/*
+ * hcn.h -- C ABI of the MI355X complex double-double / quad-double Newton
+ * corrector for polynomial homotopy continuation.
+ *
+ * The method is the path tracker of Verschelde & Yu, "Accelerating
+ * Polynomial Homotopy Continuation on a Graphics Processing Unit with Double
+ * Double and Quad Double Arithmetic": evaluation and differentiation of a
+ * polynomial system by reverse-mode differentiation of every monomial
+ * (Section 3.2, Table 1) and summation (Section 3.3), a linear solve by
+ * modified Gram-Schmidt (Section 1; Fig. 2), Newton's method (equations (2)
+ * and (3), Fig. 2) and predictor-corrector tracking of the homotopy of
+ * equation (1) (Fig. 3, equation (4)).
+ *
+ * Numbers.  A real is P doubles, most significant limb first, the limbs
+ * non-overlapping: P = 2 is double-double (DD), P = 4 quad-double (QD).  A
+ * complex number is [2][P]: the real limbs, then the imaginary limbs.
+ *
+ * Memory.  Pointers named *_dev are device pointers (hipMalloc or a torch
+ * CUDA tensor); everything else is host memory.  Device arrays are
+ * contiguous float64 / int32 in the layouts stated per argument; B is a
+ * batch of independent problems, the leading index.  All device work is
+ * enqueued on `stream` (a hipStream_t; NULL = the null stream) and is
+ * asynchronous unless stated otherwise.
+ *
+ * Errors.  Every call returns an int: HCN_OK, a negative error code or, for
+ * outcome codes, a positive value.  Argument errors (HCN_EINVAL) are found
+ * on the host before anything is enqueued; the message is available from
+ * hcn_last_error() (thread-local).  Launch failures are HCN_EDEVICE.
+ * Per-problem outcomes (singular matrix, NaN, divergence) are written to
+ * device status arrays and never to the return value.
+ */
+#ifndef HCN_H
+#define HCN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HCN_OK 0
+#define HCN_EINVAL (-1)
+#define HCN_ENOMEM (-2)
+#define HCN_EDEVICE (-3)
+#define HCN_ESINGULAR (-4)
+#define HCN_NOT_CONVERGED 1
+#define HCN_DIVERGED 2
+#define HCN_MAX_STEPS 3
+#define HCN_STEP_TOO_SMALL 4
+#define HCN_NAN 5
+
+#define HCN_DD 2
+#define HCN_QD 4
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char *hcn_last_error(void);
+
+/* ABI version (major * 100 + minor). */
+int hcn_version(void);
+
+/* ------------------------------------------------------------------------
+ * Polynomial systems (Section 3.1: the fully expanded distributed
+ * representation; Section 3.2: monomials sorted by their number of
+ * variables, with position tables laid out for coalesced access).
+ * --------------------------------------------------------------------- */
+
+typedef struct hcn_sys_s *hcn_sys;
+
+/* Copy a system to the device.  Host tables, caller-owned, copied:
+ *   eq_ptr  [N+1]   equations as a CSR over monomials (eq_ptr[0] = 0),
+ *   mon_ptr [nmon+1] monomials as a CSR over (variable, exponent) pairs,
+ *   var, exp [npairs] variable index in 0..n-1, distinct within a
+ *           monomial, exponent 1..15; a monomial with no pair is a
+ *           constant term,
+ *   coef    [nmon][2][P] complex coefficients.
+ * Requires P in {2, 4}, 1 <= n <= N <= 4096, at most 64 pairs per monomial.
+ * The handle owns its device tables; it is immutable and may be shared by
+ * calls on any stream.  Synchronous (returns after the upload). */
+int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr,
+                 const int32_t *mon_ptr, const int32_t *var, const int32_t *exp,
+                 const double *coef);
+
+int hcn_sys_free(hcn_sys sys);
+
+typedef struct {
+    int N, n, P, nmon;
+    int max_k;        /* most variables in one monomial */
+    int nslots;       /* values plus partials written per evaluation */
+    int nnz_jac;      /* structurally non-zero Jacobian entries */
+    size_t device_bytes;
+} hcn_sys_info_t;
+
+int hcn_sys_info(hcn_sys sys, hcn_sys_info_t *info);
+
+/* Total degree of each equation (host array of N). */
+int hcn_sys_degrees(hcn_sys sys, int32_t *degrees);
+
+/* ------------------------------------------------------------------------
+ * Evaluation and differentiation (Sections 3.2-3.3): f(x) and the full
+ * Jacobian by reverse-mode differentiation of every monomial (forward,
+ * backward and cross products, Table 1) times its coefficient, then one
+ * sum per output.
+ * --------------------------------------------------------------------- */
+
+/* Workspace bytes for hcn_eval_jac with B points. */
+size_t hcn_eval_ws_bytes(hcn_sys sys, int B);
+
+/* x_dev [B][n][2][P] -> f_dev [B][N][2][P] and J_dev [B][n][N][2][P]
+ * (column-major: J[k][i] = df_i/dx_k).  J_dev may be NULL (values only is
+ * not cheaper; the entry exists for symmetry).  ws_dev: hcn_eval_ws_bytes()
+ * bytes of device memory, or NULL to let the call allocate and free it on
+ * the stream. */
+int hcn_eval_jac(hcn_sys sys, int B, const double *x_dev, double *f_dev,
+                 double *J_dev, void *ws_dev, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Linear solve by modified Gram-Schmidt (Section 1; Fig. 2,
+ * GPU_Modified_Gram_Schmidt) on the augmented matrix [A | b] followed by
+ * back substitution.
+ * --------------------------------------------------------------------- */
+
+size_t hcn_mgs_ws_bytes(int B, int N, int n, int P);
+
+/* Solve A dx = b (least squares when N > n), B independent problems.
+ *   A_dev  [B][n][N][2][P] column-major, overwritten by Q,
+ *   b_dev  [B][N][2][P], overwritten by its component orthogonal to Q,
+ *   dx_dev [B][n][2][P] solution,
+ *   R_dev  [B][n+1][n][2][P] column-major R (column j holds r_kj, k <= j;
+ *          column n holds Q^H b), or NULL,
+ *   status_dev [B] int32: HCN_OK, HCN_ESINGULAR (some r_kk zero or not
+ *          finite; dx is then undefined) or HCN_NAN.
+ * Requires 1 <= n <= N <= 4096. */
+int hcn_mgs_solve(int B, int N, int n, int P, double *A_dev, double *b_dev,
+                  double *dx_dev, double *R_dev, int32_t *status_dev,
+                  void *ws_dev, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Newton's method (equation (2); Fig. 2).  The system is either f alone
+ * (gamma == NULL) or the homotopy of equation (1),
+ *   h(x, t) = gamma (1-t)^k g(x) + t^k f(x),
+ * with the total-degree start system g_i = x_i^{d_i} - 1 (d_i the degree
+ * of f_i; requires N == n).  gamma: host [2][P].  t_dev: device [B]
+ * doubles (ignored when gamma == NULL).  Norms are infinity norms over the
+ * leading limbs of the real and imaginary parts, in double.
+ * --------------------------------------------------------------------- */
+
+size_t hcn_newton_ws_bytes(hcn_sys sys, int B);
+
+/* One iteration without tests: evaluate, solve J dx = -h, x += dx.
+ *   x_dev [B][n][2][P] updated in place,
+ *   norms_dev [B][2] doubles: ||h(x)|| before the update and ||dx||,
+ *   status_dev [B]: HCN_OK, HCN_ESINGULAR or HCN_NAN (x unchanged). */
+int hcn_newton_step(hcn_sys sys, const double *gamma, int relax_k, int B,
+                    const double *t_dev, double *x_dev, double *norms_dev,
+                    int32_t *status_dev, void *ws_dev, size_t ws_bytes,
+                    void *stream);
+
+typedef struct {
+    int max_iter;       /* iterations (evaluations) at most */
+    double tol_res;     /* success when ||h|| < tol_res */
+    double tol_dx;      /* success when ||dx|| < tol_dx */
+    double max_eq_val;  /* fail when ||h|| exceeds the previous one,
+                           initially max_eq_val */
+} hcn_newton_params;
+
+/* Fig. 2 per problem, every decision taken on the device:
+ *   status_dev [B]: HCN_OK (converged), HCN_DIVERGED, HCN_NOT_CONVERGED,
+ *                   HCN_ESINGULAR or HCN_NAN,
+ *   iters_dev  [B]: evaluations performed,
+ *   norms_dev  [B][2]: last residual norm and last update norm. */
+int hcn_newton(hcn_sys sys, const double *gamma, int relax_k, int B,
+               const double *t_dev, double *x_dev, const hcn_newton_params *prm,
+               double *norms_dev, int32_t *status_dev, int32_t *iters_dev,
+               void *ws_dev, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Path tracking (Fig. 3 with the step bounds of equation (4)), the step
+ * size controlled on the device: trial t = min(1, t_acc + dt); linear
+ * extrapolation through the two last accepted points (constant before the
+ * second); Fig. 2 corrector; on success accept and, once more than two
+ * successes are counted, double dt up to max_dt; on failure reset the count
+ * and halve dt, failing below min_dt; fail after more than max_steps steps.
+ * At t = 1 Newton's method refines with end_tol and end_iters.
+ * --------------------------------------------------------------------- */
+
+typedef struct {
+    int max_iter;
+    double tol_res, tol_dx, max_eq_val, max_dt, min_dt;
+    int max_steps, end_iters;
+    double end_tol;
+    int predictor_order;  /* 0: constant, 1: linear (secant) */
+} hcn_track_params;
+
+typedef struct {
+    int32_t status;       /* HCN_OK, HCN_MAX_STEPS, HCN_STEP_TOO_SMALL, HCN_NAN */
+    int32_t steps;        /* predictor-corrector steps taken */
+    int32_t newton_iters; /* evaluations while tracking */
+    int32_t end_iters;    /* evaluations of the refinement at t = 1 */
+    int32_t end_status;   /* Fig. 2 outcome of the refinement */
+    int32_t accepted;     /* accepted steps */
+    double t;             /* last accepted t */
+    double res_norm, dx_norm;
+} hcn_path_result;
+
+size_t hcn_track_ws_bytes(hcn_sys sys, int B);
+
+/* Track B paths of the homotopy from the start solutions x0_dev
+ * [B][n][2][P] (solutions of g) to x_out_dev [B][n][2][P]; results_dev [B]
+ * hcn_path_result in device memory.  The host only enqueues steps and
+ * polls a device counter of unfinished paths: it blocks until every path
+ * has finished. */
+int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B,
+                    const double *x0_dev, const hcn_track_params *prm,
+                    double *x_out_dev, hcn_path_result *results_dev,
+                    void *ws_dev, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Elementwise arithmetic (the DD/QD layer itself, Section 3.1), for
+ * checking it bit for bit.  op codes: 0 add, 1 sub, 2 mul, 3 div, 4 sqrt
+ * (a only), 5 mul by double (b_dev: [count] doubles); on complex numbers
+ * [count][2][P]: 10 add, 11 sub, 12 mul, 13 conj(a) * b, 14 |a|^2 (out:
+ * real [count][P]), 15 real scaling (b_dev: real [count][P]); error-free
+ * transformations on doubles [count] -> [count][2]: 20 TwoSum, 21
+ * FastTwoSum, 22 TwoProd.
+ * --------------------------------------------------------------------- */
+int hcn_elementwise(int op, int P, int count, const double *a_dev,
+                    const double *b_dev, double *out_dev, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HCN_H */

@@ -1,0 +1,666 @@
+// capi.hip -- host side of the C ABI declared in include/hcn.h: argument
+// checks, system tables, workspace layout and the launch sequences of the
+// evaluation, solve, Newton and tracking entry points.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace hcn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int dev_fail(int err, const char *where) {
+    if (err == 0) return HCN_OK;
+    return fail(HCN_EDEVICE, "%s: %s", where, hipGetErrorString((hipError_t)err));
+}
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// carves consecutive 256-byte-aligned pieces out of one buffer
+struct Carver {
+    char *base;
+    size_t off = 0;
+    explicit Carver(void *b) : base((char *)b) {}
+    template <class T>
+    T *take(size_t count) {
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += align_up(count * sizeof(T));
+        return p;
+    }
+};
+
+// workspace given by the caller, or allocated on the stream for this call
+struct Workspace {
+    void *ptr = nullptr;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    int acquire(void *user, size_t user_bytes, size_t need, hipStream_t s) {
+        stream = s;
+        if (user) {
+            if (user_bytes < need)
+                return fail(HCN_EINVAL, "workspace too small: %zu bytes given, %zu needed",
+                            user_bytes, need);
+            ptr = user;
+            return HCN_OK;
+        }
+        if (need == 0) return HCN_OK;
+        hipError_t e = hipMallocAsync(&ptr, need, s);
+        if (e != hipSuccess) return fail(HCN_ENOMEM, "workspace allocation of %zu bytes failed", need);
+        owned = true;
+        return HCN_OK;
+    }
+    ~Workspace() {
+        if (owned && ptr) (void)hipFreeAsync(ptr, stream);
+    }
+};
+
+}  // namespace
+
+struct hcn_sys_s {
+    SysView v;
+    void *dmem = nullptr;
+    size_t bytes = 0;
+    int nnz = 0;
+    std::vector<int32_t> deg;
+};
+
+extern "C" {
+
+const char *hcn_last_error(void) { return g_err.c_str(); }
+
+int hcn_version(void) { return 100; }
+
+int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const int32_t *mon_ptr,
+                 const int32_t *var, const int32_t *exp, const double *coef) {
+    if (!out) return fail(HCN_EINVAL, "hcn_sys_load: out is NULL");
+    *out = nullptr;
+    if (P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_sys_load: P must be 2 or 4, got %d", P);
+    if (n < 1 || N < n || N > 4096)
+        return fail(HCN_EINVAL, "hcn_sys_load: need 1 <= n <= N <= 4096 (N=%d n=%d)", N, n);
+    if (!eq_ptr || !mon_ptr || !coef) return fail(HCN_EINVAL, "hcn_sys_load: NULL table");
+    if (eq_ptr[0] != 0) return fail(HCN_EINVAL, "hcn_sys_load: eq_ptr[0] must be 0");
+    for (int i = 0; i < N; ++i)
+        if (eq_ptr[i + 1] < eq_ptr[i]) return fail(HCN_EINVAL, "hcn_sys_load: eq_ptr not monotone");
+    const int nmon = eq_ptr[N];
+    if (nmon < 1) return fail(HCN_EINVAL, "hcn_sys_load: no monomials");
+    if (mon_ptr[0] != 0) return fail(HCN_EINVAL, "hcn_sys_load: mon_ptr[0] must be 0");
+    int max_k = 0;
+    for (int m = 0; m < nmon; ++m) {
+        const int k = mon_ptr[m + 1] - mon_ptr[m];
+        if (k < 0 || k > 64)
+            return fail(HCN_EINVAL, "hcn_sys_load: monomial %d has %d pairs (0..64 allowed)", m, k);
+        max_k = std::max(max_k, k);
+    }
+    const int npairs = mon_ptr[nmon];
+    if (npairs > 0 && (!var || !exp)) return fail(HCN_EINVAL, "hcn_sys_load: NULL var/exp");
+    {
+        std::vector<int> seen(n, -1);
+        for (int m = 0; m < nmon; ++m)
+            for (int q = mon_ptr[m]; q < mon_ptr[m + 1]; ++q) {
+                if (var[q] < 0 || var[q] >= n)
+                    return fail(HCN_EINVAL, "hcn_sys_load: variable %d out of range", var[q]);
+                if (exp[q] < 1 || exp[q] > 15)
+                    return fail(HCN_EINVAL, "hcn_sys_load: exponent %d out of 1..15", exp[q]);
+                if (seen[var[q]] == m)
+                    return fail(HCN_EINVAL, "hcn_sys_load: variable %d repeated in monomial %d",
+                                var[q], m);
+                seen[var[q]] = m;
+            }
+    }
+    const int W = 2 * P;
+
+    // sort monomials by number of variables (stable)
+    std::vector<int> perm(nmon), inv(nmon), eq_of(nmon);
+    for (int i = 0; i < N; ++i)
+        for (int m = eq_ptr[i]; m < eq_ptr[i + 1]; ++m) eq_of[m] = i;
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+        return (mon_ptr[a + 1] - mon_ptr[a]) < (mon_ptr[b + 1] - mon_ptr[b]);
+    });
+    for (int s = 0; s < nmon; ++s) inv[perm[s]] = s;
+
+    std::vector<int32_t> h_k(nmon), h_slot(nmon), h_stride(nmon);
+    long nslots = 0;
+    for (int s = 0; s < nmon;) {
+        const int k = mon_ptr[perm[s] + 1] - mon_ptr[perm[s]];
+        int e = s;
+        while (e < nmon && mon_ptr[perm[e] + 1] - mon_ptr[perm[e]] == k) ++e;
+        const int Mg = e - s;
+        for (int q = s; q < e; ++q) {
+            h_k[q] = k;
+            h_slot[q] = (int32_t)(nslots + (q - s));
+            h_stride[q] = Mg;
+        }
+        nslots += (long)(k + 1) * Mg;
+        s = e;
+    }
+    if (nslots > (1L << 30)) return fail(HCN_EINVAL, "hcn_sys_load: system too large");
+    const int kk = std::max(max_k, 1);
+    std::vector<uint16_t> h_pos((size_t)kk * nmon, 0);
+    std::vector<uint8_t> h_ex((size_t)kk * nmon, 0);
+    std::vector<double> h_coef((size_t)nmon * W);
+    for (int s = 0; s < nmon; ++s) {
+        const int m = perm[s];
+        for (int p = 0; p < h_k[s]; ++p) {
+            h_pos[(size_t)p * nmon + s] = (uint16_t)var[mon_ptr[m] + p];
+            h_ex[(size_t)p * nmon + s] = (uint8_t)exp[mon_ptr[m] + p];
+        }
+        std::memcpy(&h_coef[(size_t)s * W], coef + (size_t)m * W, sizeof(double) * W);
+    }
+    // sums: value slots per equation, partial slots per dense Jacobian entry
+    std::vector<int32_t> f_ptr(N + 1, 0), f_list(nmon);
+    for (int i = 0; i < N; ++i) {
+        f_ptr[i + 1] = eq_ptr[i + 1];
+        for (int m = eq_ptr[i]; m < eq_ptr[i + 1]; ++m) f_list[m] = h_slot[inv[m]];
+    }
+    const long nJ = (long)n * N;
+    std::vector<int32_t> J_ptr(nJ + 1, 0), J_list(std::max(npairs, 1));
+    for (int m = 0; m < nmon; ++m)
+        for (int q = mon_ptr[m]; q < mon_ptr[m + 1]; ++q) J_ptr[(long)var[q] * N + eq_of[m] + 1] += 1;
+    for (long e = 0; e < nJ; ++e) J_ptr[e + 1] += J_ptr[e];
+    int nnz = 0;
+    for (long e = 0; e < nJ; ++e) nnz += J_ptr[e + 1] > J_ptr[e] ? 1 : 0;
+    {
+        std::vector<int32_t> fill(J_ptr.begin(), J_ptr.end() - 1);
+        for (int i = 0; i < N; ++i)
+            for (int m = eq_ptr[i]; m < eq_ptr[i + 1]; ++m) {
+                const int s = inv[m];
+                for (int p = 0; p < h_k[s]; ++p) {
+                    const long e = (long)var[mon_ptr[m] + p] * N + i;
+                    J_list[fill[e]++] = h_slot[s] + (p + 1) * h_stride[s];
+                }
+            }
+    }
+    std::vector<int32_t> deg(N, 0);
+    for (int i = 0; i < N; ++i)
+        for (int m = eq_ptr[i]; m < eq_ptr[i + 1]; ++m) {
+            int d = 0;
+            for (int q = mon_ptr[m]; q < mon_ptr[m + 1]; ++q) d += exp[q];
+            deg[i] = std::max(deg[i], d);
+        }
+
+    // one device allocation for every table
+    Carver c(nullptr);
+    c.take<int32_t>(nmon);
+    c.take<int32_t>(nmon);
+    c.take<int32_t>(nmon);
+    c.take<uint16_t>(h_pos.size());
+    c.take<uint8_t>(h_ex.size());
+    c.take<double>(h_coef.size());
+    c.take<int32_t>(f_ptr.size());
+    c.take<int32_t>(f_list.size());
+    c.take<int32_t>(J_ptr.size());
+    c.take<int32_t>(J_list.size());
+    c.take<int32_t>(deg.size());
+    const size_t bytes = c.off;
+    void *dmem = nullptr;
+    if (hipMalloc(&dmem, bytes) != hipSuccess)
+        return fail(HCN_ENOMEM, "hcn_sys_load: device allocation of %zu bytes failed", bytes);
+    Carver d(dmem);
+    auto up = [&](auto *dst, const auto &vec) {
+        return hipMemcpy(dst, vec.data(), vec.size() * sizeof(vec[0]), hipMemcpyHostToDevice);
+    };
+    auto *d_k = d.take<int32_t>(nmon);
+    auto *d_slot = d.take<int32_t>(nmon);
+    auto *d_stride = d.take<int32_t>(nmon);
+    auto *d_pos = d.take<uint16_t>(h_pos.size());
+    auto *d_ex = d.take<uint8_t>(h_ex.size());
+    auto *d_coef = d.take<double>(h_coef.size());
+    auto *d_fptr = d.take<int32_t>(f_ptr.size());
+    auto *d_flist = d.take<int32_t>(f_list.size());
+    auto *d_Jptr = d.take<int32_t>(J_ptr.size());
+    auto *d_Jlist = d.take<int32_t>(J_list.size());
+    auto *d_deg = d.take<int32_t>(deg.size());
+    hipError_t e = hipSuccess;
+    e = e ? e : up(d_k, h_k);
+    e = e ? e : up(d_slot, h_slot);
+    e = e ? e : up(d_stride, h_stride);
+    e = e ? e : up(d_pos, h_pos);
+    e = e ? e : up(d_ex, h_ex);
+    e = e ? e : up(d_coef, h_coef);
+    e = e ? e : up(d_fptr, f_ptr);
+    e = e ? e : up(d_flist, f_list);
+    e = e ? e : up(d_Jptr, J_ptr);
+    e = e ? e : up(d_Jlist, J_list);
+    e = e ? e : up(d_deg, deg);
+    if (e != hipSuccess) {
+        (void)hipFree(dmem);
+        return dev_fail(e, "hcn_sys_load: upload");
+    }
+    auto *sys = new hcn_sys_s;
+    sys->dmem = dmem;
+    sys->bytes = bytes;
+    sys->nnz = nnz;
+    sys->deg = deg;
+    SysView &v = sys->v;
+    v.N = N;
+    v.n = n;
+    v.P = P;
+    v.nmon = nmon;
+    v.max_k = max_k;
+    v.nslots = (int)nslots;
+    v.mon_k = d_k;
+    v.mon_slot = d_slot;
+    v.mon_stride = d_stride;
+    v.pos = d_pos;
+    v.ex = d_ex;
+    v.coef = d_coef;
+    v.f_ptr = d_fptr;
+    v.f_list = d_flist;
+    v.J_ptr = d_Jptr;
+    v.J_list = d_Jlist;
+    v.deg = d_deg;
+    *out = sys;
+    return HCN_OK;
+}
+
+int hcn_sys_free(hcn_sys sys) {
+    if (!sys) return HCN_OK;
+    (void)hipFree(sys->dmem);
+    delete sys;
+    return HCN_OK;
+}
+
+int hcn_sys_info(hcn_sys sys, hcn_sys_info_t *info) {
+    if (!sys || !info) return fail(HCN_EINVAL, "hcn_sys_info: NULL argument");
+    info->N = sys->v.N;
+    info->n = sys->v.n;
+    info->P = sys->v.P;
+    info->nmon = sys->v.nmon;
+    info->max_k = sys->v.max_k;
+    info->nslots = sys->v.nslots;
+    info->nnz_jac = sys->nnz;
+    info->device_bytes = sys->bytes;
+    return HCN_OK;
+}
+
+int hcn_sys_degrees(hcn_sys sys, int32_t *degrees) {
+    if (!sys || !degrees) return fail(HCN_EINVAL, "hcn_sys_degrees: NULL argument");
+    std::memcpy(degrees, sys->deg.data(), sizeof(int32_t) * sys->deg.size());
+    return HCN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// workspace layouts
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct EvalWs {
+    double *scratch;
+    double *norm_part;
+};
+
+template <class C>
+EvalWs carve_eval(C &c, const SysView &v, int B) {
+    EvalWs w;
+    w.scratch = c.template take<double>((size_t)B * v.nslots * 2 * v.P);
+    w.norm_part = c.template take<double>((size_t)B * sum_nparts(v));
+    return w;
+}
+
+struct NewtonWs {
+    EvalWs ev;
+    double *Jaug, *R, *inv, *dx;
+    PathState *st;
+};
+
+template <class C>
+NewtonWs carve_newton(C &c, const SysView &v, int B) {
+    NewtonWs w;
+    const size_t W = 2 * v.P;
+    w.ev = carve_eval(c, v, B);
+    w.Jaug = c.template take<double>((size_t)B * (v.n + 1) * v.N * W);
+    w.R = c.template take<double>((size_t)B * (v.n + 1) * v.n * W);
+    w.inv = c.template take<double>((size_t)B * v.n * v.P);
+    w.dx = c.template take<double>((size_t)B * v.n * W);
+    w.st = c.template take<PathState>((size_t)B);
+    return w;
+}
+
+struct TrackWs {
+    NewtonWs nw;
+    double *x, *x_acc, *x_prev, *t;
+    int32_t *count;
+};
+
+template <class C>
+TrackWs carve_track(C &c, const SysView &v, int B) {
+    TrackWs w;
+    const size_t W = 2 * v.P;
+    w.nw = carve_newton(c, v, B);
+    w.x = c.template take<double>((size_t)B * v.n * W);
+    w.x_acc = c.template take<double>((size_t)B * v.n * W);
+    w.x_prev = c.template take<double>((size_t)B * v.n * W);
+    w.t = c.template take<double>((size_t)B);
+    w.count = c.template take<int32_t>(1);
+    return w;
+}
+
+// evaluation of f (or h) and J into the augmented [J | -h] of the Newton
+// workspace, with the residual norm parts
+int enqueue_eval_aug(const SysView &v, int B, const double *x, const Homotopy &hom,
+                     const NewtonWs &w, const PathState *st, hipStream_t s) {
+    const long W = 2 * v.P;
+    int e = launch_mon(v.P, v, B, x, v.n * W, w.ev.scratch, (long)v.nslots * W, st, s);
+    if (e) return dev_fail(e, "evaluation launch");
+    e = launch_sum(v.P, v, B, w.ev.scratch, (long)v.nslots * W, x, v.n * W, hom, w.Jaug,
+                   v.N * W, (long)(v.n + 1) * v.N * W, w.Jaug + (size_t)v.n * v.N * W,
+                   (long)(v.n + 1) * v.N * W, 1, w.ev.norm_part, st, s);
+    if (e) return dev_fail(e, "summation launch");
+    return HCN_OK;
+}
+
+MgsArgs newton_mgs_args(const SysView &v, int B, const NewtonWs &w, double *x, int mode) {
+    const long W = 2 * v.P;
+    MgsArgs a = {};
+    a.B = B;
+    a.N = v.N;
+    a.n = v.n;
+    a.mode = mode;
+    a.A = w.Jaug;
+    a.A_cstride = v.N * W;
+    a.A_pstride = (long)(v.n + 1) * v.N * W;
+    a.bcol = nullptr;
+    a.R = w.R;
+    a.R_pstride = (long)(v.n + 1) * v.n * W;
+    a.inv = w.inv;
+    a.inv_pstride = (long)v.n * v.P;
+    a.dx = w.dx;
+    a.dx_pstride = v.n * W;
+    a.x = x;
+    a.x_pstride = v.n * W;
+    a.norm_part = w.ev.norm_part;
+    a.nparts = sum_nparts(v);
+    a.st = w.st;
+    return a;
+}
+
+int make_homotopy(const SysView &v, const double *gamma, int relax_k, const double *t,
+                  Homotopy &hom) {
+    std::memset(&hom, 0, sizeof hom);
+    if (!gamma) return HCN_OK;
+    if (v.N != v.n) return fail(HCN_EINVAL, "homotopy with the total-degree start system needs N == n");
+    if (relax_k < 1) return fail(HCN_EINVAL, "relaxation exponent k must be >= 1");
+    if (!t) return fail(HCN_EINVAL, "homotopy needs a device array of t values");
+    hom.on = 1;
+    hom.relax_k = relax_k;
+    std::memcpy(hom.gamma, gamma, sizeof(double) * 2 * v.P);
+    hom.t = t;
+    return HCN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hcn_eval_ws_bytes(hcn_sys sys, int B) {
+    if (!sys || B < 0) return 0;
+    Carver c(nullptr);
+    carve_eval(c, sys->v, B);
+    return c.off;
+}
+
+int hcn_eval_jac(hcn_sys sys, int B, const double *x, double *f, double *J, void *ws,
+                 size_t ws_bytes, void *stream) {
+    if (!sys) return fail(HCN_EINVAL, "hcn_eval_jac: NULL system");
+    if (B < 0) return fail(HCN_EINVAL, "hcn_eval_jac: negative batch");
+    if (B == 0) return HCN_OK;
+    if (!x || !f) return fail(HCN_EINVAL, "hcn_eval_jac: NULL x or f");
+    const SysView &v = sys->v;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace wsp;
+    int rc = wsp.acquire(ws, ws_bytes, hcn_eval_ws_bytes(sys, B), s);
+    if (rc) return rc;
+    Carver c(wsp.ptr);
+    EvalWs w = carve_eval(c, v, B);
+    const long W = 2 * v.P;
+    int e = launch_mon(v.P, v, B, x, v.n * W, w.scratch, (long)v.nslots * W, nullptr, s);
+    if (e) return dev_fail(e, "hcn_eval_jac: evaluation launch");
+    Homotopy hom;
+    std::memset(&hom, 0, sizeof hom);
+    e = launch_sum(v.P, v, B, w.scratch, (long)v.nslots * W, x, v.n * W, hom, J, v.N * W,
+                   (long)v.n * v.N * W, f, v.N * W, 0, nullptr, nullptr, s);
+    if (e) return dev_fail(e, "hcn_eval_jac: summation launch");
+    return HCN_OK;
+}
+
+size_t hcn_mgs_ws_bytes(int B, int N, int n, int P) {
+    if (B < 0 || n < 1 || (P != 2 && P != 4)) return 0;
+    Carver c(nullptr);
+    c.take<double>((size_t)B * (n + 1) * n * 2 * P);
+    c.take<double>((size_t)B * n * P);
+    return c.off;
+}
+
+int hcn_mgs_solve(int B, int N, int n, int P, double *A, double *b, double *dx, double *R,
+                  int32_t *status, void *ws, size_t ws_bytes, void *stream) {
+    if (P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_mgs_solve: P must be 2 or 4");
+    if (n < 1 || N < n || N > 4096)
+        return fail(HCN_EINVAL, "hcn_mgs_solve: need 1 <= n <= N <= 4096 (N=%d n=%d)", N, n);
+    if (B < 0) return fail(HCN_EINVAL, "hcn_mgs_solve: negative batch");
+    if (B == 0) return HCN_OK;
+    if (!A || !b || !dx) return fail(HCN_EINVAL, "hcn_mgs_solve: NULL A, b or dx");
+    hipStream_t s = (hipStream_t)stream;
+    Workspace wsp;
+    int rc = wsp.acquire(ws, ws_bytes, hcn_mgs_ws_bytes(B, N, n, P), s);
+    if (rc) return rc;
+    Carver c(wsp.ptr);
+    double *Rw = c.take<double>((size_t)B * (n + 1) * n * 2 * P);
+    double *inv = c.take<double>((size_t)B * n * P);
+    const long W = 2 * P;
+    MgsArgs a = {};
+    a.B = B;
+    a.N = N;
+    a.n = n;
+    a.mode = MGS_SOLVE;
+    a.A = A;
+    a.A_cstride = N * W;
+    a.A_pstride = (long)n * N * W;
+    a.bcol = b;
+    a.b_pstride = N * W;
+    a.R = R ? R : Rw;
+    a.R_pstride = (long)(n + 1) * n * W;
+    a.inv = inv;
+    a.inv_pstride = (long)n * P;
+    a.dx = dx;
+    a.dx_pstride = n * W;
+    a.status = status;
+    return dev_fail(launch_mgs(P, a, s), "hcn_mgs_solve: launch");
+}
+
+size_t hcn_newton_ws_bytes(hcn_sys sys, int B) {
+    if (!sys || B < 0) return 0;
+    Carver c(nullptr);
+    carve_newton(c, sys->v, B);
+    return c.off;
+}
+
+int hcn_newton_step(hcn_sys sys, const double *gamma, int relax_k, int B, const double *t,
+                    double *x, double *norms, int32_t *status, void *ws, size_t ws_bytes,
+                    void *stream) {
+    if (!sys) return fail(HCN_EINVAL, "hcn_newton_step: NULL system");
+    if (B < 0) return fail(HCN_EINVAL, "hcn_newton_step: negative batch");
+    if (B == 0) return HCN_OK;
+    if (!x) return fail(HCN_EINVAL, "hcn_newton_step: NULL x");
+    const SysView &v = sys->v;
+    Homotopy hom;
+    int rc = make_homotopy(v, gamma, relax_k, t, hom);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace wsp;
+    rc = wsp.acquire(ws, ws_bytes, hcn_newton_ws_bytes(sys, B), s);
+    if (rc) return rc;
+    Carver c(wsp.ptr);
+    NewtonWs w = carve_newton(c, v, B);
+    rc = enqueue_eval_aug(v, B, x, hom, w, nullptr, s);
+    if (rc) return rc;
+    MgsArgs a = newton_mgs_args(v, B, w, x, MGS_NEWTON_STEP);
+    a.norms = norms;
+    a.status = status;
+    return dev_fail(launch_mgs(v.P, a, s), "hcn_newton_step: solve launch");
+}
+
+int hcn_newton(hcn_sys sys, const double *gamma, int relax_k, int B, const double *t, double *x,
+               const hcn_newton_params *prm, double *norms, int32_t *status, int32_t *iters,
+               void *ws, size_t ws_bytes, void *stream) {
+    if (!sys || !prm) return fail(HCN_EINVAL, "hcn_newton: NULL system or parameters");
+    if (B < 0) return fail(HCN_EINVAL, "hcn_newton: negative batch");
+    if (prm->max_iter < 0 || prm->max_iter > 1000)
+        return fail(HCN_EINVAL, "hcn_newton: max_iter out of 0..1000");
+    if (B == 0) return HCN_OK;
+    if (!x) return fail(HCN_EINVAL, "hcn_newton: NULL x");
+    const SysView &v = sys->v;
+    Homotopy hom;
+    int rc = make_homotopy(v, gamma, relax_k, t, hom);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace wsp;
+    rc = wsp.acquire(ws, ws_bytes, hcn_newton_ws_bytes(sys, B), s);
+    if (rc) return rc;
+    Carver c(wsp.ptr);
+    NewtonWs w = carve_newton(c, v, B);
+    int e = launch_newton_init(B, w.st, *prm, s);
+    if (e) return dev_fail(e, "hcn_newton: init launch");
+    const MgsArgs a = newton_mgs_args(v, B, w, x, MGS_NEWTON_FIG2);
+    for (int it = 0; it < prm->max_iter; ++it) {
+        rc = enqueue_eval_aug(v, B, x, hom, w, w.st, s);
+        if (rc) return rc;
+        e = launch_mgs(v.P, a, s);
+        if (e) return dev_fail(e, "hcn_newton: solve launch");
+    }
+    e = launch_newton_finish(B, w.st, norms, status, iters, s);
+    return dev_fail(e, "hcn_newton: finish launch");
+}
+
+size_t hcn_track_ws_bytes(hcn_sys sys, int B) {
+    if (!sys || B < 0) return 0;
+    Carver c(nullptr);
+    carve_track(c, sys->v, B);
+    return c.off;
+}
+
+int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B, const double *x0,
+                    const hcn_track_params *prm, double *x_out, hcn_path_result *results,
+                    void *ws, size_t ws_bytes, void *stream) {
+    if (!sys || !prm || !gamma) return fail(HCN_EINVAL, "hcn_track_paths: NULL system, gamma or parameters");
+    if (B < 0) return fail(HCN_EINVAL, "hcn_track_paths: negative batch");
+    if (prm->max_iter < 1 || prm->max_iter > 100)
+        return fail(HCN_EINVAL, "hcn_track_paths: max_iter out of 1..100");
+    if (prm->max_steps < 0 || prm->end_iters < 0 || prm->end_iters > 1000)
+        return fail(HCN_EINVAL, "hcn_track_paths: bad max_steps or end_iters");
+    if (!(prm->max_dt > 0.0) || !(prm->min_dt > 0.0) || prm->max_dt > 1.0)
+        return fail(HCN_EINVAL, "hcn_track_paths: need 0 < min_dt and 0 < max_dt <= 1");
+    if (B == 0) return HCN_OK;
+    if (!x0 || !x_out || !results) return fail(HCN_EINVAL, "hcn_track_paths: NULL x0, x_out or results");
+    const SysView &v = sys->v;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace wsp;
+    int rc = wsp.acquire(ws, ws_bytes, hcn_track_ws_bytes(sys, B), s);
+    if (rc) return rc;
+    Carver c(wsp.ptr);
+    TrackWs w = carve_track(c, v, B);
+    Homotopy hom;
+    rc = make_homotopy(v, gamma, relax_k, w.t, hom);
+    if (rc) return rc;
+    TrackArgs ta = {};
+    ta.B = B;
+    ta.n = v.n;
+    ta.P = v.P;
+    ta.max_iter = prm->max_iter;
+    ta.max_steps = prm->max_steps;
+    ta.end_iters = prm->end_iters;
+    ta.predictor_order = prm->predictor_order;
+    ta.tol_res = prm->tol_res;
+    ta.tol_dx = prm->tol_dx;
+    ta.max_eq_val = prm->max_eq_val;
+    ta.max_dt = prm->max_dt;
+    ta.min_dt = prm->min_dt;
+    ta.end_tol = prm->end_tol;
+    ta.st = w.nw.st;
+    ta.x = w.x;
+    ta.x_acc = w.x_acc;
+    ta.x_prev = w.x_prev;
+    ta.x_out = x_out;
+    ta.t = w.t;
+    ta.res = results;
+    ta.active_count = w.count;
+    int e = launch_track_init(ta, x0, s);
+    if (e) return dev_fail(e, "hcn_track_paths: init launch");
+    const MgsArgs a = newton_mgs_args(v, B, w.nw, w.x, MGS_NEWTON_FIG2);
+    int32_t *host_count = nullptr;
+    if (hipHostMalloc((void **)&host_count, sizeof(int32_t)) != hipSuccess)
+        return fail(HCN_ENOMEM, "hcn_track_paths: pinned allocation failed");
+    // every path ends within max_steps + 1 tracking steps plus the steps of
+    // its refinement; the bound only guards against a logic error
+    const long max_total = (long)prm->max_steps + 3 + (prm->end_iters + prm->max_iter - 1) / prm->max_iter + 2;
+    const int chunk = 8;
+    long done_steps = 0;
+    rc = HCN_OK;
+    while (done_steps < max_total) {
+        for (int q = 0; q < chunk && rc == HCN_OK; ++q) {
+            e = launch_track_begin(ta, s);
+            if (e) { rc = dev_fail(e, "hcn_track_paths: begin launch"); break; }
+            for (int it = 0; it < prm->max_iter && rc == HCN_OK; ++it) {
+                rc = enqueue_eval_aug(v, B, w.x, hom, w.nw, w.nw.st, s);
+                if (rc) break;
+                e = launch_mgs(v.P, a, s);
+                if (e) rc = dev_fail(e, "hcn_track_paths: solve launch");
+            }
+            if (rc) break;
+            e = launch_track_end(ta, s);
+            if (e) rc = dev_fail(e, "hcn_track_paths: end launch");
+        }
+        if (rc) break;
+        done_steps += chunk;
+        e = launch_track_count(ta, s);
+        if (e) { rc = dev_fail(e, "hcn_track_paths: count launch"); break; }
+        e = hipMemcpyAsync(host_count, w.count, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+        if (!e) e = hipStreamSynchronize(s);
+        if (e) { rc = dev_fail(e, "hcn_track_paths: poll"); break; }
+        if (*host_count == 0) break;
+    }
+    if (rc == HCN_OK && *host_count != 0)
+        rc = fail(HCN_EDEVICE, "hcn_track_paths: %d paths unfinished after %ld steps", *host_count,
+                  done_steps);
+    (void)hipHostFree(host_count);
+    return rc;
+}
+
+int hcn_elementwise(int op, int P, int count, const double *a, const double *b, double *out,
+                    void *stream) {
+    if (P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_elementwise: P must be 2 or 4");
+    static const int ops[] = {0, 1, 2, 3, 4, 5, 10, 11, 12, 13, 14, 15, 20, 21, 22};
+    if (std::find(std::begin(ops), std::end(ops), op) == std::end(ops))
+        return fail(HCN_EINVAL, "hcn_elementwise: unknown op %d", op);
+    if (count < 0) return fail(HCN_EINVAL, "hcn_elementwise: negative count");
+    if (count == 0) return HCN_OK;
+    const bool needs_b = !(op == 4 || op == 14);
+    if (!a || !out || (needs_b && !b)) return fail(HCN_EINVAL, "hcn_elementwise: NULL array");
+    return dev_fail(launch_elementwise(op, P, count, a, b, out, (hipStream_t)stream),
+                    "hcn_elementwise: launch");
+}
+
+}  // extern "C"

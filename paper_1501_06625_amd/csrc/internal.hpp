@@ -1,0 +1,121 @@
+// internal.hpp -- structures shared by the host API and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/hcn.h"
+
+namespace hcn {
+
+// Device view of a loaded system.  Monomials are stored sorted by their
+// number of variables k (Section 3.2: threads of one block get products of
+// similar size); `perm` maps a sorted monomial back to its input index.
+// Per monomial m (sorted order):
+//   mon_k[m]      number of variables,
+//   mon_slot[m]   slot of its value; partial p is at mon_slot + (p+1)*mon_stride,
+//   mon_stride[m] size of its group of equal k (slots of a group are laid out
+//                 position-major so that lanes of a wavefront write
+//                 consecutive slots at the same step, Section 3.2),
+//   pos[p*nmon+m] variable of position p, ex[p*nmon+m] its exponent,
+//   coef[m]       [2][P] coefficient.
+// Sums (Section 3.3): the value slots of equation i are
+// f_list[f_ptr[i] .. f_ptr[i+1]); the partial slots of the dense Jacobian
+// entry e = k*N + i (column-major) are J_list[J_ptr[e] .. J_ptr[e+1]), in
+// input monomial order.
+struct SysView {
+    int N, n, P, nmon, max_k, nslots;
+    const int32_t *mon_k;
+    const int32_t *mon_slot;
+    const int32_t *mon_stride;
+    const uint16_t *pos;
+    const uint8_t *ex;
+    const double *coef;
+    const int32_t *f_ptr;
+    const int32_t *f_list;
+    const int32_t *J_ptr;
+    const int32_t *J_list;
+    const int32_t *deg;
+};
+
+// Homotopy h = gamma (1-t)^k g + t^k f with g_i = x_i^{d_i} - 1.
+struct Homotopy {
+    int on;            // 0: plain f
+    int relax_k;
+    double gamma[8];   // [2][P]
+    const double *t;   // device [B]
+};
+
+// Per-path corrector (Fig. 2) and tracker (Fig. 3) state, in device memory.
+struct PathState {
+    // corrector
+    double last, res, dxn, tol_res, tol_dx;
+    int32_t c_status, c_iter, c_active, c_maxit;
+    // tracker
+    double t_acc, t_prev, dt, t;
+    int32_t phase, nsucc, steps, accepted, newton_iters, end_iters, end_status,
+        have_prev, status, refine_started, finalized;
+};
+
+enum { PHASE_TRACK = 0, PHASE_REFINE = 1, PHASE_DONE = 2 };
+enum { C_RUNNING = 100 };
+
+enum MgsMode { MGS_SOLVE = 0, MGS_NEWTON_STEP = 1, MGS_NEWTON_FIG2 = 2 };
+
+struct MgsArgs {
+    int B, N, n, mode;
+    double *A;          // column j of path b: A + b*A_pstride + j*A_cstride
+    long A_cstride, A_pstride;
+    double *bcol;       // column n when separate (else column n of A)
+    long b_pstride;
+    double *R;          // [B][n+1][n][2P]
+    long R_pstride;
+    double *inv;        // [B][n][P] 1/r_kk
+    long inv_pstride;
+    double *dx;         // [B][n][2P]
+    long dx_pstride;
+    int32_t *status;    // [B] or NULL
+    double *x;          // Newton: [B][n][2P] updated in place
+    long x_pstride;
+    const double *norm_part;  // Newton: [B][nparts] partial residual maxima
+    int nparts;
+    double *norms;      // Newton step: [B][2]
+    PathState *st;      // Fig. 2 mode
+};
+
+// launchers (return hipError_t as int)
+int launch_mon(int P, const SysView &s, int B, const double *x, long x_pstride,
+               double *scratch, long sc_pstride, const PathState *st,
+               hipStream_t stream);
+int launch_sum(int P, const SysView &s, int B, const double *scratch, long sc_pstride,
+               const double *x, long x_pstride, const Homotopy &hom, double *J,
+               long J_cstride, long J_pstride, double *f, long f_pstride, int f_neg,
+               double *norm_part, const PathState *st, hipStream_t stream);
+int sum_nparts(const SysView &s);
+int launch_mgs(int P, const MgsArgs &a, hipStream_t stream);
+int launch_elementwise(int op, int P, int count, const double *a, const double *b,
+                       double *out, hipStream_t stream);
+
+// tracker kernels
+struct TrackArgs {
+    int B, n, P, max_iter, max_steps, end_iters, predictor_order;
+    double tol_res, tol_dx, max_eq_val, max_dt, min_dt, end_tol;
+    PathState *st;
+    double *x;       // working point [B][n][2P]
+    double *x_acc;   // last accepted
+    double *x_prev;  // the one before
+    double *x_out;
+    double *t;       // trial t per path [B]
+    hcn_path_result *res;
+    int32_t *active_count;
+};
+int launch_newton_init(int B, PathState *st, const hcn_newton_params &p, hipStream_t s);
+int launch_newton_finish(int B, const PathState *st, double *norms, int32_t *status,
+                         int32_t *iters, hipStream_t s);
+int launch_track_init(const TrackArgs &a, const double *x0, hipStream_t s);
+int launch_track_begin(const TrackArgs &a, hipStream_t s);
+int launch_track_end(const TrackArgs &a, hipStream_t s);
+int launch_track_count(const TrackArgs &a, hipStream_t s);
+
+}  // namespace hcn

@@ -1,0 +1,382 @@
+"""GPU (HIP, through the C ABI) against the CPU oracle.
+
+Bars: elementwise DD/QD operations bit for bit; reductions (f, J) within
+1e-28 (DD) / 1e-58 (QD) of the sum of the magnitudes of their terms; solves
+by normwise backward error <= 1e-28 / 1e-58 and forward difference to the
+oracle <= max(1e-28, 16 n kappa u); Newton and tracking decisions equal.
+"""
+import mpmath
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from oracle import mpref as M
+from paper_1501_06625_amd import systems as S
+from tests.gpu_util import GATE, UNIT, limb_diff, lead_complex, term_scales, random_points
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1501_06625_amd import hcn
+    return hcn
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+# ---------------------------------------------------------------------------
+# arithmetic layer: bit for bit
+# ---------------------------------------------------------------------------
+
+def _rand_reals(rng, cnt, P, spread=30):
+    hi = rng.standard_normal(cnt) * np.exp2(rng.integers(-spread, spread, cnt))
+    out = np.zeros((cnt, P))
+    out[:, 0] = hi
+    prev = hi
+    for j in range(1, P):
+        nxt = np.spacing(np.abs(prev)) * rng.uniform(-0.5, 0.5, cnt)
+        out[:, j] = nxt
+        prev = np.where(nxt == 0, prev, nxt)
+    # edge cases: zeros, powers of two, exact negatives
+    out[:8] = 0.0
+    out[8:16, 0] = np.exp2(np.arange(8) - 4)
+    out[8:16, 1:] = 0.0
+    return out
+
+
+def _bitwise_equal(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.array_equal(a, b) or bool(np.all((a == b) | (np.isnan(a) & np.isnan(b))))
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_elementwise_bitwise(H, P):
+    rng = np.random.default_rng(1000 + P)
+    cnt = 20000
+    a = _rand_reals(rng, cnt, P)
+    b = _rand_reals(rng, cnt, P)
+    # cancellation partners: b = -a + tiny
+    b[100:600] = -a[100:600]
+    b[100:600, P - 1] += np.spacing(np.abs(a[100:600, P - 1])) * 3
+    bsafe = np.where(np.abs(b[:, :1]) > 0, b, 1.0)
+    for op, x, y in (("add", a, b), ("sub", a, b), ("mul", a, b), ("div", a, bsafe)):
+        g = host(H.elementwise(op, P, dev(x), dev(y)))
+        o = O.elementwise(op, P, x, y)
+        assert _bitwise_equal(g, o), op
+    pos = np.where(a[:, :1] < 0, -a, a)
+    assert _bitwise_equal(host(H.elementwise("sqrt", P, dev(pos))), O.elementwise("sqrt", P, pos))
+    d = rng.standard_normal(cnt) * np.exp2(rng.integers(-10, 10, cnt))
+    assert _bitwise_equal(host(H.elementwise("mul_d", P, dev(a), dev(d))),
+                          O.elementwise("mul_d", P, a, d))
+    ca = _rand_reals(rng, 2 * cnt, P).reshape(cnt, 2, P)
+    cb = _rand_reals(rng, 2 * cnt, P).reshape(cnt, 2, P)
+    for op in ("cadd", "csub", "cmul", "cmul_conj"):
+        assert _bitwise_equal(host(H.elementwise(op, P, dev(ca), dev(cb))),
+                              O.elementwise(op, P, ca, cb)), op
+    assert _bitwise_equal(host(H.elementwise("cnorm2", P, dev(ca))), O.elementwise("cnorm2", P, ca))
+    assert _bitwise_equal(host(H.elementwise("cscale", P, dev(ca), dev(a))),
+                          O.elementwise("cscale", P, ca, a))
+
+
+def test_eft_bitwise(H):
+    rng = np.random.default_rng(7)
+    a = rng.standard_normal(50000) * np.exp2(rng.integers(-60, 60, 50000))
+    b = rng.standard_normal(50000) * np.exp2(rng.integers(-60, 60, 50000))
+    for op in ("two_sum", "two_prod"):
+        assert _bitwise_equal(host(H.elementwise(op, 2, dev(a), dev(b))), O.elementwise(op, 2, a, b))
+    big = np.where(np.abs(a) >= np.abs(b), a, b)
+    sm = np.where(np.abs(a) >= np.abs(b), b, a)
+    assert _bitwise_equal(host(H.elementwise("fast_two_sum", 2, dev(big), dev(sm))),
+                          O.elementwise("fast_two_sum", 2, big, sm))
+
+
+# ---------------------------------------------------------------------------
+# evaluation and differentiation
+# ---------------------------------------------------------------------------
+
+def _ragged_system(P, seed=4):
+    """Monomials of 0..20 variables (several k-groups, constants, k = 1,
+    and more than 16 variables), exponents 1..3."""
+    rng = np.random.default_rng(seed)
+    n = N = 24
+    eqs = []
+    for i in range(N):
+        mons = [[]]  # a constant term
+        seen = set()
+        for _ in range(int(rng.integers(3, 12))):
+            k = int(rng.choice([1, 2, 3, 5, 8, 13, 17, 20]))
+            vs = tuple(sorted(rng.choice(n, size=k, replace=False).tolist()))
+            if vs in seen:
+                continue
+            seen.add(vs)
+            mons.append([(v, int(rng.integers(1, 4))) for v in vs])
+        eqs.append(mons)
+    nmon = sum(len(m) for m in eqs)
+    coefs = S.unit_complex(rng.uniform(0, 6.28, nmon), P)
+    return S.system_from_monomials(N, n, P, eqs, coefs, name="ragged")
+
+
+def _check_eval(H, ps, xs):
+    P = ps.P
+    sysd = H.System(ps)
+    f, J = H.eval_jac(sysd, dev(xs))
+    f, J = host(f), host(J)
+    for b in range(xs.shape[0]):
+        fo, Jo = O.eval_jac(ps, xs[b])
+        Sf, SJ = term_scales(ps, xs[b])
+        ef = np.abs(limb_diff(f[b], fo))
+        eJ = np.abs(limb_diff(J[b], Jo))
+        assert np.all(ef <= GATE[P] * Sf + 1e-300), (b, ef.max())
+        assert np.all(eJ <= GATE[P] * SJ + 1e-300), (b, eJ.max())
+        # structural zeros are exact zeros
+        assert np.all(J[b][SJ == 0] == 0)
+    sysd.free()
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_eval_small_track_system(H, P):
+    ps = S.small_track_system(1, P)
+    xs = random_points(np.random.default_rng(3), 5, ps.n, P)
+    _check_eval(H, ps, xs)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_eval_dense32(H, P):
+    ps = S.dense32_system(0, P)
+    xs = S.dense32_points(0, 2, P)
+    _check_eval(H, ps, xs)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_eval_ragged(H, P):
+    ps = _ragged_system(P)
+    xs = random_points(np.random.default_rng(5), 3, ps.n, P)
+    # also a non-unit point to exercise magnitudes
+    xs[2] *= 1.3
+    _check_eval(H, ps, xs)
+
+
+def test_eval_sparse512_sampled(H):
+    """Full-size sparse system: every output checked (the oracle's plain
+    evaluation of this system is cheap)."""
+    ps = S.sparse512_system(0, 2)
+    xs = random_points(np.random.default_rng(9), 1, ps.n, 2)
+    _check_eval(H, ps, xs)
+
+
+def test_eval_batch_independent_and_deterministic(H):
+    ps = S.dense32_system(0, 2)
+    xs = S.dense32_points(1, 6, 2)
+    sysd = H.System(ps)
+    f, J = H.eval_jac(sysd, dev(xs))
+    f2, J2 = H.eval_jac(sysd, dev(xs))
+    assert _bitwise_equal(host(f), host(f2)) and _bitwise_equal(host(J), host(J2))
+    f1, J1 = H.eval_jac(sysd, dev(xs[3]))
+    assert _bitwise_equal(host(f1), host(f)[3]) and _bitwise_equal(host(J1), host(J)[3])
+
+
+# ---------------------------------------------------------------------------
+# modified Gram-Schmidt solve
+# ---------------------------------------------------------------------------
+
+def _rand_matrix(rng, N, n, P):
+    return random_points(rng, n, N, P) * rng.uniform(0.3, 1.0, (n, N, 1, 1))
+
+
+def _backward_error(A, b, dx):
+    """||A dx - b||_inf / (||A||_inf ||dx||_inf + ||b||_inf) at 320 bits."""
+    Am, xm = M.colmajor(A), mpmath.matrix(M.vec(dx))
+    bm = mpmath.matrix(M.vec(b))
+    r = Am * xm - bm
+    num = max(abs(r[i]) for i in range(r.rows))
+    nA = max(sum(abs(Am[i, j]) for j in range(Am.cols)) for i in range(Am.rows))
+    nx = max(abs(xm[i]) for i in range(xm.rows))
+    nb = max(abs(bm[i]) for i in range(bm.rows))
+    return float(num / (nA * nx + nb))
+
+
+@pytest.mark.parametrize("P,N,n", [(2, 8, 8), (2, 32, 32), (2, 40, 24), (4, 16, 16), (2, 1, 1),
+                                   (4, 33, 33)])
+def test_mgs_parity(H, P, N, n):
+    rng = np.random.default_rng(N * 7 + n + P)
+    B = 3
+    A = np.stack([_rand_matrix(rng, N, n, P) for _ in range(B)])
+    b = random_points(rng, B, N, P)
+    Ad, bd = dev(A), dev(b)
+    dx, R, status = H.mgs_solve(Ad, bd)
+    dx, R, status = host(dx), host(R), host(status)
+    assert np.all(status == 0)
+    for q in range(B):
+        rc, dxo, Qo, Ro, _ = O.mgs_solve(P, A[q], b[q])
+        assert rc == 0
+        if N == n:
+            assert _backward_error(A[q], b[q], dx[q]) <= GATE[P]
+        Z = lead_complex(A[q]).T
+        kappa = np.linalg.cond(Z)
+        tol = max(GATE[P], 16 * n * kappa * UNIT[P])
+        scale = np.abs(lead_complex(dxo)).max()
+        assert np.abs(limb_diff(dx[q], dxo)).max() <= tol * scale
+        assert np.abs(limb_diff(R[q], Ro)).max() <= tol * np.abs(lead_complex(Ro)).max()
+
+
+def test_mgs_singular_and_empty(H):
+    import torch
+    rng = np.random.default_rng(2)
+    A = np.stack([_rand_matrix(rng, 6, 6, 2) for _ in range(2)])
+    A[1, 3] = 0.0
+    b = random_points(rng, 2, 6, 2)
+    dx, R, status = H.mgs_solve(dev(A), dev(b))
+    st = host(status)
+    assert st[0] == H.OK and st[1] == H.ESINGULAR
+    # an empty batch is a no-op
+    dx, R, status = H.mgs_solve(torch.zeros((0, 2, 2, 2, 2), dtype=torch.float64, device="cuda"),
+                                torch.zeros((0, 2, 2, 2), dtype=torch.float64, device="cuda"))
+    assert dx.shape[0] == 0
+
+
+# ---------------------------------------------------------------------------
+# Newton
+# ---------------------------------------------------------------------------
+
+def _kappa_at(ps, x):
+    _, J = O.eval_jac(ps, x)
+    return np.linalg.cond(lead_complex(J).T)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_newton_step_dense32(H, P):
+    ps = S.dense32_system(0, P)
+    xs = S.dense32_points(2, 2, P)
+    sysd = H.System(ps)
+    xd = dev(xs)
+    norms, status = H.newton_step(sysd, xd)
+    xg, norms, status = host(xd), host(norms), host(status)
+    assert np.all(status == 0)
+    for q in range(xs.shape[0]):
+        rc, xo, no = O.newton_step(ps, None, None, 1, 1.0, xs[q])
+        assert rc == 0
+        kappa = _kappa_at(ps, xs[q])
+        tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
+        assert np.abs(limb_diff(xg[q], xo)).max() <= tol * no[1]
+        assert abs(norms[q, 0] - no[0]) <= 1e-14 * no[0]
+        assert abs(norms[q, 1] - no[1]) <= 1e-10 * no[1]
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_newton_step_homotopy(H, P):
+    ps = S.small_track_system(2, P)
+    g = O.total_degree_start(ps)
+    rng = S.rng_for(0, 77)
+    gam = S.random_unit_gamma(rng, P)
+    xs = S.start_solution(rng, S.degrees(ps), P)[None].repeat(3, 0)
+    xs[:, :, 0, 0] += 1e-3 * rng.standard_normal((3, ps.n))
+    ts = np.array([0.0, 0.25, 0.6])
+    import torch
+    sysd = H.System(ps)
+    xd = dev(xs)
+    norms, status = H.newton_step(sysd, xd, gamma=gam, t=dev(ts))
+    xg = host(xd)
+    for q in range(3):
+        rc, xo, no = O.newton_step(ps, g, gam, 1, float(ts[q]), xs[q])
+        h, Jh = O.eval_h(ps, g, gam, 1, float(ts[q]), xs[q])
+        kappa = np.linalg.cond(lead_complex(Jh).T)
+        tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
+        assert np.abs(limb_diff(xg[q], xo)).max() <= tol * max(no[1], 1e-300)
+
+
+def test_newton_fig2_decisions(H):
+    P = 2
+    ps = S.small_track_system(3, P)
+    g = O.total_degree_start(ps)
+    rng = S.rng_for(0, 78)
+    gam = S.random_unit_gamma(rng, P)
+    B = 12
+    base = S.start_solution(rng, S.degrees(ps), P)
+    xs = base[None].repeat(B, 0)
+    scale = np.logspace(-8, -1, B)
+    xs[:, :, 0, 0] += scale[:, None] * rng.standard_normal((B, ps.n))
+    ts = np.linspace(0.0, 0.05, B)
+    sysd = H.System(ps)
+    xd = dev(xs)
+    status, iters, norms = H.newton(sysd, xd, gamma=gam, t=dev(ts), max_iter=4)
+    status, iters, xg = host(status), host(iters), host(xd)
+    for q in range(B):
+        xo, r = O.newton(ps, g, gam, 1, float(ts[q]), xs[q], max_iter=4)
+        assert status[q] == r.status and iters[q] == r.iters, (q, status[q], r.status)
+        assert np.abs(limb_diff(xg[q], xo)).max() <= 1e-20 * max(1.0, np.abs(lead_complex(xo)).max())
+
+
+# ---------------------------------------------------------------------------
+# tracking
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_track_closed_form_powers(H, P):
+    rng = S.rng_for(6, 50 + P)
+    n, d = 4, 3
+    cs = S.unit_complex(rng.uniform(0, 6.28, n), P)
+    ps = S.diagonal_power_system(cs, d, P)
+    gam = S.random_unit_gamma(rng, P)
+    x0 = np.stack([S.start_solution(rng, np.full(n, d), P) for _ in range(3)])
+    sysd = H.System(ps)
+    xo, res = H.track_paths(sysd, gam, dev(x0))
+    xo = host(xo)
+    for q in range(3):
+        assert res[q]["status"] == H.OK and res[q]["t"] == 1.0
+        for i in range(n):
+            ref = M.closed_form_endpoint(M.mp_complex(gam), M.mp_complex(cs[i]), d,
+                                         M.mp_complex(x0[q, i]), steps=1500)
+            assert abs(M.mp_complex(xo[q, i]) - ref) <= GATE[P]
+        # and the same decisions as the oracle
+        xr, r = O.track(ps, O.total_degree_start(ps), gam, 1, x0[q])
+        assert (res[q]["steps"], res[q]["accepted"], res[q]["newton_iters"]) == \
+               (r.steps, r.accepted, r.newton_iters)
+
+
+@pytest.mark.parametrize("seed", [0, 3, 5, 6])
+def test_track_small_system_parity(H, seed):
+    P = 2
+    ps = S.small_track_system(seed, P)
+    g = O.total_degree_start(ps)
+    rng = S.rng_for(0, 100 + seed)
+    gam = S.random_unit_gamma(rng, P)
+    x0 = S.ones_point(ps.n, P)
+    sysd = H.System(ps)
+    xg, res = H.track_paths(sysd, gam, dev(x0[None]))
+    xg, res = host(xg)[0], res[0]
+    xo, r = O.track(ps, g, gam, 1, x0)
+    assert res["status"] == r.status
+    assert (res["steps"], res["accepted"], res["newton_iters"]) == (r.steps, r.accepted, r.newton_iters)
+    assert res["end_status"] == r.end_status and res["end_iters"] == r.end_iters
+    if r.status == O.OK:
+        scale = max(1.0, np.abs(lead_complex(xo)).max())
+        tol = 1e-26 if r.end_status == O.OK else 1e-8
+        assert np.abs(limb_diff(xg, xo)).max() <= tol * scale
+
+
+def test_track_batch_matches_single(H):
+    """Paths of one system tracked together give the same results as alone."""
+    P = 2
+    ps = S.small_track_system(5, P)
+    rng = S.rng_for(0, 200)
+    gam = S.random_unit_gamma(rng, P)
+    degs = S.degrees(ps)
+    x0 = np.stack([S.start_solution(rng, degs, P) for _ in range(4)])
+    sysd = H.System(ps)
+    xb, rb = H.track_paths(sysd, gam, dev(x0))
+    xb = host(xb)
+    for q in (0, 3):
+        x1, r1 = H.track_paths(sysd, gam, dev(x0[q:q + 1]))
+        assert _bitwise_equal(host(x1)[0], xb[q])
+        assert r1[0].tobytes() == rb[q].tobytes()
