@@ -1,0 +1,222 @@
+#!/usr/bin/env python3
+"""Benchmark: complex double-double Newton steps per second.
+
+Workload: the dense n = 32 random system (32 monomials per equation, each
+a product of 16 distinct variables with exponents uniform in {1, 2, 3},
+unit-circle coefficients) and B = 10240 distinct random unit-modulus
+points.  One benchmark step applies one complete Newton step (evaluation
+and differentiation by reverse mode, summation, modified Gram-Schmidt
+solve, back substitution, update) to every point, starting each step from
+the same points, so every step does the same work.  Inputs are resident in
+device memory before the timed region.
+
+Reported beside it: the same in quad-double (2048 points), the latency of
+one Newton step of a single path, the roofline position of the dominant
+kernel (algorithmic FP64 operations of one launch over its mean HIP-event
+duration, against the FP64 vector peak) and the CPU oracle timed on this
+host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+B_DD = 10240
+B_QD = 2048
+
+
+def cpu_baseline(target_s: float = 15.0) -> dict:
+    """The oracle's Newton step (plain evaluation + MGS, own DD arithmetic)
+    on distinct points of the same system, one thread per core (the oracle
+    is C called through ctypes, which releases the GIL)."""
+    from oracle import oracle as O
+    from paper_1501_06625_amd import systems as S
+
+    ps = S.dense32_system(0, 2)
+    ref = O.SysRef(ps)
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    cores = max(1, min(cores, 16))
+    pts = S.dense32_points(7, cores, 2)
+    t0 = time.perf_counter()
+    O.newton_step(ref, None, None, 1, 1.0, pts[0])
+    one = time.perf_counter() - t0
+    per_thread = max(1, int(target_s / max(one, 1e-6) / 1.0))
+    per_thread = min(per_thread, 2000)
+    done = [0] * cores
+
+    def work(c):
+        for _ in range(per_thread):
+            O.newton_step(ref, None, None, 1, 1.0, pts[c])
+            done[c] += 1
+
+    threads = [threading.Thread(target=work, args=(c,)) for c in range(cores)]
+    t0 = time.perf_counter()
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    wall = time.perf_counter() - t0
+    total = sum(done)
+    return {"value": total / wall, "unit": "steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"{total} complex-DD Newton steps of the dense n=32 system "
+                      f"({per_thread} per thread on {cores} threads), {wall:.1f} s wall"}
+
+
+def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single")) -> dict:
+    import numpy as np
+    import torch
+    from paper_1501_06625_amd import flops, hcn, systems as S
+
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    out = {}
+
+    def leg(P: int, B: int, K: int, W: int, profile: bool):
+        ps = S.dense32_system(0, P)
+        pts = S.dense32_points(0, B, P)
+        sysd = hcn.System(ps)
+        x0 = torch.from_numpy(pts).to(dev)
+        x = torch.empty_like(x0)
+        ws = hcn.newton_ws(sysd, B)
+        for _ in range(W):
+            x.copy_(x0)
+            hcn.newton_step(sysd, x, ws=ws)
+        torch.cuda.synchronize()
+        if profile:
+            hcn.profile_reset()
+            hcn.profile_enable(True)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        start.record()
+        for _ in range(K):
+            x.copy_(x0)
+            norms, status = hcn.newton_step(sysd, x, ws=ws)
+        stop.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ev_ms = start.elapsed_time(stop)
+        kern = {}
+        if profile:
+            hcn.profile_enable(False)
+            for name in ("eval_monomials", "eval_sums", "mgs"):
+                ms, cnt = hcn.profile_query(name)
+                kern[name] = (ms, cnt)
+            hcn.profile_reset()
+        ok = int((status == 0).sum().item())
+        fl = flops.newton_step(ps, P)
+        sysd.free()
+        return dict(ms_per_step=ev_ms / K, wall_s=wall, B=B, ok=ok, flops=fl, kern=kern)
+
+    if "dd" in legs:
+        out["dd"] = leg(2, B_DD, steps, warmup, profile=True)
+    if "qd" in legs:
+        out["qd"] = leg(4, B_QD, qd_steps, 1, profile=False)
+    if "single" in legs:
+        # single-path latency: one Newton step of one point, stream-ordered
+        out["single"] = leg(2, 1, 200, 5, profile=False)
+    return out
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--qd-steps", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--legs", default="dd,qd,single",
+                    help="comma list of dd (the reported line), qd, single; profiling runs use one")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
+              "(paths are independent: a multi-GPU run would shard them, see the design notes)",
+              file=sys.stderr)
+        return 2
+    rank = int(os.environ.get("RANK", "0"))
+    cpu = None
+    if rank == 0 and not args.no_cpu:
+        # before the GPU is touched
+        cpu = cpu_baseline()
+    legs = tuple(args.legs.split(","))
+    if "dd" not in legs:
+        legs = ("dd",) + legs
+    r = run_gpu(args.steps, args.warmup, args.qd_steps, legs)
+    dd = r["dd"]
+    ms = dd["ms_per_step"]
+    value = dd["B"] / (ms / 1e3)
+    # dominant kernel by measured time
+    kern = dd["kern"]
+    dom = max(kern, key=lambda k: kern[k][0])
+    dom_ms, dom_cnt = kern[dom]
+    avg_ms = dom_ms / max(dom_cnt, 1)
+    flops_launch = dd["flops"][dom] * dd["B"]
+    achieved = flops_launch / (avg_ms / 1e3) / 1e12
+    total_tflops = dd["flops"]["total"] * dd["B"] / (ms / 1e3) / 1e12
+    qd = r.get("qd")
+    single = r.get("single")
+    line = {
+        "metric": "complex-DD Newton steps/s",
+        "value": value,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "dense n=32 random system (32 monomials/equation, 16 distinct "
+                        "variables/monomial, exponents 1..3, unit-circle coefficients); one "
+                        f"complex-DD Newton step (eval_jac + mgs_solve + update) at each of "
+                        f"{dd['B']} distinct unit-modulus points per step",
+            "precision": "complex double-double",
+            "points_per_step": dd["B"],
+            "seed": 1000,
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": dom,
+            "achieved": achieved,
+            "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / FP64_PEAK_TFLOPS,
+            "traffic": None,
+            "avg_launch_ms": avg_ms,
+            "flops_per_launch": flops_launch,
+        },
+        "cpu_baseline": cpu,
+        "pct_fp64_peak": 100.0 * total_tflops / FP64_PEAK_TFLOPS,
+        "kernels_ms_per_launch": {k: v[0] / max(v[1], 1) for k, v in kern.items()},
+        "algorithmic_mflop_per_newton_step": dd["flops"]["total"] / 1e6,
+        "converged_or_ok_points": dd["ok"],
+        "qd": None if qd is None else {
+            "steps_per_s": qd["B"] / (qd["ms_per_step"] / 1e3), "points": qd["B"],
+            "ms_per_step": qd["ms_per_step"],
+            "pct_fp64_peak": 100.0 * qd["flops"]["total"] * qd["B"] /
+            (qd["ms_per_step"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS},
+        "single_path_us_per_newton_step": None if single is None else single["ms_per_step"] * 1e3,
+    }
+    if rank == 0:
+        print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -227,6 +227,17 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B,
 int hcn_elementwise(int op, int P, int count, const double *a_dev,
                     const double *b_dev, double *out_dev, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Kernel timing (measurement support, not part of the method).  When
+ * enabled, every kernel launch of the library is bracketed by two HIP
+ * events recorded on its launch stream.  Kernel names: "eval_monomials",
+ * "eval_sums", "mgs".  hcn_profile_query waits for the recorded events and
+ * returns the summed event time of one kernel name and its launch count.
+ * --------------------------------------------------------------------- */
+int hcn_profile_enable(int on);
+int hcn_profile_reset(void);
+int hcn_profile_query(const char *kernel, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

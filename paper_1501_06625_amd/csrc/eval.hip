@@ -19,6 +19,7 @@
 // fused into the same pass.
 #include "internal.hpp"
 #include "mp.hpp"
+#include "prof.hpp"
 
 namespace hcn {
 
@@ -234,6 +235,7 @@ static int launch_mon_t(const SysView &s, int B, const double *x, long x_pstride
                         long sc_pstride, const PathState *st, hipStream_t stream) {
     if (s.nmon == 0 || B == 0) return 0;
     dim3 grid((s.nmon + 255) / 256, B < 65535 ? B : 65535);
+    ProfScope prof("eval_monomials", stream);
     const int kb = kbucket(s.max_k);
     constexpr bool isdd = limbs<R>::P == 2;
     switch (kb) {
@@ -263,6 +265,7 @@ int launch_sum(int P, const SysView &s, int B, const double *scratch, long sc_ps
                const PathState *st, hipStream_t stream) {
     if (B == 0) return 0;
     dim3 grid(sum_nparts(s), B < 65535 ? B : 65535);
+    ProfScope prof("eval_sums", stream);
     if (P == 2)
         hipLaunchKernelGGL(k_sum<dd>, grid, dim3(256), 0, stream, s, B, scratch, sc_pstride, x,
                            x_pstride, hom, J, J_cstride, J_pstride, f, f_pstride, f_neg, norm_part,

@@ -13,6 +13,7 @@
 // y_i -= r_ik dx_k for i < k.
 #include "internal.hpp"
 #include "mp.hpp"
+#include "prof.hpp"
 
 namespace hcn {
 
@@ -240,6 +241,7 @@ __global__ __launch_bounds__(MGS_THREADS) void k_mgs(MgsArgs a) {
 
 int launch_mgs(int P, const MgsArgs &a, hipStream_t stream) {
     if (a.B == 0) return 0;
+    ProfScope prof("mgs", stream);
     if (P == 2)
         hipLaunchKernelGGL(k_mgs<dd>, dim3(a.B), dim3(MGS_THREADS), 0, stream, a);
     else

@@ -62,7 +62,8 @@ assert PATH_RESULT_DTYPE.itemsize == 48
 EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn_sys_info",
            "hcn_sys_degrees", "hcn_eval_ws_bytes", "hcn_eval_jac", "hcn_mgs_ws_bytes",
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
-           "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise"]
+           "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
+           "hcn_profile_reset", "hcn_profile_query"]
 
 
 def _load():
@@ -91,6 +92,9 @@ def _load():
     lib.hcn_track_paths.argtypes = [vp, vp, ci, ci, vp, ctypes.POINTER(_TrackParams), vp, vp, vp,
                                     sz, vp]
     lib.hcn_elementwise.argtypes = [ci, ci, ci, vp, vp, vp, vp]
+    lib.hcn_profile_enable.argtypes = [ci]
+    lib.hcn_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(cd),
+                                      ctypes.POINTER(ctypes.c_int64)]
     return lib
 
 
@@ -317,3 +321,19 @@ def elementwise(op: str, P: int, a: torch.Tensor, b: Optional[torch.Tensor] = No
     bb = b.contiguous() if b is not None else None
     _check(_lib.hcn_elementwise(code, P, count, _ptr(a), _ptr(bb), _ptr(out), _stream()))
     return out
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(_lib.hcn_profile_enable(1 if on else 0))
+
+
+def profile_reset() -> None:
+    _check(_lib.hcn_profile_reset())
+
+
+def profile_query(kernel: str):
+    """(summed event milliseconds, launches) of one kernel name."""
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(_lib.hcn_profile_query(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
+    return ms.value, cnt.value
