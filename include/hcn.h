@@ -135,6 +135,16 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A_dev, double *b_dev,
                   double *dx_dev, double *R_dev, int32_t *status_dev,
                   void *ws_dev, size_t ws_bytes, void *stream);
 
+/* Select the MGS variant used by every solve (process-wide): 0 automatic
+ * (2 for large single problems, else 1), 1 one workgroup per problem,
+ * 2 right-looking across workgroups (one launch per column step, the
+ * trailing matrix re-read every step), 3 column-resident across workgroups
+ * (one cooperative launch per problem; each workgroup keeps its columns in
+ * LDS).  Variants 2 and 3 give bitwise identical results; 1 differs from
+ * them only by the rounding of its reductions.  3 falls back to 2 when the
+ * columns do not fit in LDS. */
+int hcn_set_mgs_variant(int variant);
+
 /* ------------------------------------------------------------------------
  * Newton's method (equation (2); Fig. 2).  The system is either f alone
  * (gamma == NULL) or the homotopy of equation (1),

@@ -74,6 +74,16 @@ struct Workspace {
     }
 };
 
+int g_mgs_variant = 0;  // 0 auto, 1 workgroup per problem, 2 right-looking, 3 column-resident
+
+// choose and launch the MGS variant for B problems of size N x n
+int enqueue_mgs(int P, const MgsArgs &a, int *ints, hipStream_t s) {
+    int v = g_mgs_variant;
+    if (v == 0) v = (a.n >= 160 && a.B <= 4) ? 3 : 1;
+    if (v == 1) return launch_mgs(P, a, s);
+    return launch_mgs_big(P, a, v, ints, s);
+}
+
 }  // namespace
 
 struct hcn_sys_s {
@@ -325,6 +335,7 @@ struct NewtonWs {
     EvalWs ev;
     double *Jaug, *R, *inv, *dx;
     PathState *st;
+    int *ints;
 };
 
 template <class C>
@@ -337,6 +348,7 @@ NewtonWs carve_newton(C &c, const SysView &v, int B) {
     w.inv = c.template take<double>((size_t)B * v.n * v.P);
     w.dx = c.template take<double>((size_t)B * v.n * W);
     w.st = c.template take<PathState>((size_t)B);
+    w.ints = c.template take<int>((size_t)2 * B + 1);
     return w;
 }
 
@@ -452,6 +464,7 @@ size_t hcn_mgs_ws_bytes(int B, int N, int n, int P) {
     Carver c(nullptr);
     c.take<double>((size_t)B * (n + 1) * n * 2 * P);
     c.take<double>((size_t)B * n * P);
+    c.take<int>((size_t)2 * B + 1);
     return c.off;
 }
 
@@ -470,6 +483,7 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A, double *b, double *dx, 
     Carver c(wsp.ptr);
     double *Rw = c.take<double>((size_t)B * (n + 1) * n * 2 * P);
     double *inv = c.take<double>((size_t)B * n * P);
+    int *ints = c.take<int>((size_t)2 * B + 1);
     const long W = 2 * P;
     MgsArgs a = {};
     a.B = B;
@@ -488,7 +502,7 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A, double *b, double *dx, 
     a.dx = dx;
     a.dx_pstride = n * W;
     a.status = status;
-    return dev_fail(launch_mgs(P, a, s), "hcn_mgs_solve: launch");
+    return dev_fail(enqueue_mgs(P, a, ints, s), "hcn_mgs_solve: launch");
 }
 
 size_t hcn_newton_ws_bytes(hcn_sys sys, int B) {
@@ -520,7 +534,7 @@ int hcn_newton_step(hcn_sys sys, const double *gamma, int relax_k, int B, const 
     MgsArgs a = newton_mgs_args(v, B, w, x, MGS_NEWTON_STEP);
     a.norms = norms;
     a.status = status;
-    return dev_fail(launch_mgs(v.P, a, s), "hcn_newton_step: solve launch");
+    return dev_fail(enqueue_mgs(v.P, a, w.ints, s), "hcn_newton_step: solve launch");
 }
 
 int hcn_newton(hcn_sys sys, const double *gamma, int relax_k, int B, const double *t, double *x,
@@ -548,7 +562,7 @@ int hcn_newton(hcn_sys sys, const double *gamma, int relax_k, int B, const doubl
     for (int it = 0; it < prm->max_iter; ++it) {
         rc = enqueue_eval_aug(v, B, x, hom, w, w.st, s);
         if (rc) return rc;
-        e = launch_mgs(v.P, a, s);
+        e = enqueue_mgs(v.P, a, w.ints, s);
         if (e) return dev_fail(e, "hcn_newton: solve launch");
     }
     e = launch_newton_finish(B, w.st, norms, status, iters, s);
@@ -626,7 +640,7 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B, const 
             for (int it = 0; it < prm->max_iter && rc == HCN_OK; ++it) {
                 rc = enqueue_eval_aug(v, B, w.x, hom, w.nw, w.nw.st, s);
                 if (rc) break;
-                e = launch_mgs(v.P, a, s);
+                e = enqueue_mgs(v.P, a, w.nw.ints, s);
                 if (e) rc = dev_fail(e, "hcn_track_paths: solve launch");
             }
             if (rc) break;
@@ -647,6 +661,12 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B, const 
                   done_steps);
     (void)hipHostFree(host_count);
     return rc;
+}
+
+int hcn_set_mgs_variant(int variant) {
+    if (variant < 0 || variant > 3) return fail(HCN_EINVAL, "hcn_set_mgs_variant: 0..3");
+    g_mgs_variant = variant;
+    return HCN_OK;
 }
 
 int hcn_elementwise(int op, int P, int count, const double *a, const double *b, double *out,

@@ -94,6 +94,11 @@ int launch_sum(int P, const SysView &s, int B, const double *scratch, long sc_ps
                double *norm_part, const PathState *st, hipStream_t stream);
 int sum_nparts(const SysView &s);
 int launch_mgs(int P, const MgsArgs &a, hipStream_t stream);
+// multi-workgroup MGS for large single problems: variant 2 right-looking
+// (one launch per column step), 3 column-resident (cooperative); ints_dev
+// holds 2B+1 ints of workspace
+int launch_mgs_big(int P, const MgsArgs &a, int variant, int *ints_dev, hipStream_t stream);
+size_t mgs_res_lds(int N, int n, int P);
 int launch_elementwise(int op, int P, int count, const double *a, const double *b,
                        double *out, hipStream_t stream);
 

@@ -63,6 +63,7 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_sys_degrees", "hcn_eval_ws_bytes", "hcn_eval_jac", "hcn_mgs_ws_bytes",
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
+           "hcn_set_mgs_variant",
            "hcn_profile_reset", "hcn_profile_query"]
 
 
@@ -93,6 +94,7 @@ def _load():
                                     sz, vp]
     lib.hcn_elementwise.argtypes = [ci, ci, ci, vp, vp, vp, vp]
     lib.hcn_profile_enable.argtypes = [ci]
+    lib.hcn_set_mgs_variant.argtypes = [ci]
     lib.hcn_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(cd),
                                       ctypes.POINTER(ctypes.c_int64)]
     return lib
@@ -337,3 +339,11 @@ def profile_query(kernel: str):
     cnt = ctypes.c_int64()
     _check(_lib.hcn_profile_query(kernel.encode(), ctypes.byref(ms), ctypes.byref(cnt)))
     return ms.value, cnt.value
+
+
+MGS_AUTO, MGS_WORKGROUP, MGS_RIGHT_LOOKING, MGS_COLUMN_RESIDENT = 0, 1, 2, 3
+
+
+def set_mgs_variant(variant: int) -> None:
+    """Process-wide MGS variant (see hcn_set_mgs_variant)."""
+    _check(_lib.hcn_set_mgs_variant(int(variant)))

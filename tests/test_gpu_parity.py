@@ -380,3 +380,79 @@ def test_track_batch_matches_single(H):
         x1, r1 = H.track_paths(sysd, gam, dev(x0[q:q + 1]))
         assert _bitwise_equal(host(x1)[0], xb[q])
         assert r1[0].tobytes() == rb[q].tobytes()
+
+
+# ---------------------------------------------------------------------------
+# large systems: multi-workgroup MGS variants
+# ---------------------------------------------------------------------------
+
+def _solve_variant(H, variant, A, b):
+    H.set_mgs_variant(variant)
+    try:
+        dx, R, status = H.mgs_solve(dev(A), dev(b))
+        return host(dx), host(R), host(status)
+    finally:
+        H.set_mgs_variant(H.MGS_AUTO)
+
+
+@pytest.mark.parametrize("P,N,n", [(2, 512, 512), (2, 300, 257), (4, 200, 200)])
+def test_mgs_big_variants_bitwise(H, P, N, n):
+    """Right-looking and column-resident variants: identical bits; the
+    one-workgroup variant within the solve tolerance."""
+    rng = np.random.default_rng(N + n + P)
+    A = _rand_matrix(rng, N, n, P)[None]
+    b = random_points(rng, 1, N, P)
+    d2, R2, s2 = _solve_variant(H, 2, A, b)
+    d3, R3, s3 = _solve_variant(H, 3, A, b)
+    assert s2[0] == 0 and s3[0] == 0
+    assert _bitwise_equal(d2, d3) and _bitwise_equal(R2, R3)
+    d1, R1, s1 = _solve_variant(H, 1, A, b)
+    kappa = np.linalg.cond(lead_complex(A[0]).T)
+    tol = max(GATE[P], 16 * n * kappa * UNIT[P])
+    assert np.abs(limb_diff(d1, d2)).max() <= tol * np.abs(lead_complex(d2)).max()
+
+
+def test_mgs_big_backward_error(H):
+    P, n = 2, 160
+    rng = np.random.default_rng(160)
+    A = _rand_matrix(rng, n, n, P)[None]
+    b = random_points(rng, 1, n, P)
+    for v in (2, 3):
+        d, _, s = _solve_variant(H, v, A, b)
+        assert s[0] == 0
+        assert _backward_error(A[0], b[0], d[0]) <= GATE[P]
+
+
+def test_mgs_big_singular(H):
+    P = 2
+    rng = np.random.default_rng(5)
+    A = _rand_matrix(rng, 200, 200, P)[None]
+    A[0, 150] = 0.0
+    b = random_points(rng, 1, 200, P)
+    for v in (2, 3):
+        _, _, s = _solve_variant(H, v, A, b)
+        assert s[0] == H.ESINGULAR
+
+
+def test_newton_step_sparse512_vs_oracle(H):
+    """The full-size sparse n = 512 Newton step (column-resident solve, the
+    configuration the benchmark times) against the oracle's plain step."""
+    P = 2
+    ps = S.sparse512_system(0, P)
+    x = random_points(np.random.default_rng(12), 1, ps.n, P)
+    sysd = H.System(ps)
+    out = {}
+    for v in (1, 3):
+        H.set_mgs_variant(v)
+        xd = dev(x)
+        norms, status = H.newton_step(sysd, xd)
+        H.set_mgs_variant(H.MGS_AUTO)
+        assert host(status)[0] == 0
+        out[v] = host(xd)[0]
+    rc, xo, no = O.newton_step(ps, None, None, 1, 1.0, x[0])
+    assert rc == 0
+    f, J = O.eval_jac(ps, x[0])
+    kappa = np.linalg.cond(lead_complex(J).T)
+    tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
+    for v in (1, 3):
+        assert np.abs(limb_diff(out[v], xo)).max() <= tol * no[1], v
