@@ -128,7 +128,51 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single"))
     if "single" in legs:
         # single-path latency: one Newton step of one point, stream-ordered
         out["single"] = leg(2, 1, 200, 5, profile=False)
+    if "sparse512" in legs:
+        out["sparse512"] = sparse512_leg(hcn, flops, S, dev)
     return out
+
+
+def sparse512_leg(hcn, flops, S, dev, reps: int = 10) -> dict:
+    """Sparse n = 512 system (4 monomials of 2 variables + a constant per
+    equation): one Newton step of one point, timed per MGS variant.  The
+    solve dominates (17.2 GFLOP of MGS against 1 MFLOP of evaluation)."""
+    import torch
+    ps = S.sparse512_system(0, 2)
+    pts = S.random_unit_point(S.rng_for(2, 99), ps.n, 2)[None]
+    sysd = hcn.System(ps)
+    x0 = torch.from_numpy(pts).to(dev)
+    x = torch.empty_like(x0)
+    ws = hcn.newton_ws(sysd, 1)
+    mgs_flops = flops.mgs_solve(ps.N, ps.n, 2)
+    res = {}
+    names = {1: "workgroup", 2: "right_looking", 3: "column_resident"}
+    for v in (1, 2, 3):
+        hcn.set_mgs_variant(v)
+        x.copy_(x0)
+        hcn.newton_step(sysd, x, ws=ws)
+        torch.cuda.synchronize()
+        hcn.profile_reset()
+        hcn.profile_enable(True)
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            x.copy_(x0)
+            hcn.newton_step(sysd, x, ws=ws)
+        stop.record()
+        torch.cuda.synchronize()
+        hcn.profile_enable(False)
+        ms_mgs, cnt = hcn.profile_query("mgs")
+        hcn.profile_reset()
+        step_ms = start.elapsed_time(stop) / reps
+        mgs_ms = ms_mgs / max(cnt, 1)
+        res[names[v]] = {"newton_step_ms": step_ms, "mgs_ms": mgs_ms,
+                         "mgs_tflops": mgs_flops / (mgs_ms / 1e3) / 1e12}
+    hcn.set_mgs_variant(0)
+    sysd.free()
+    res["mgs_gflop"] = mgs_flops / 1e9
+    return res
 
 
 def main() -> int:
@@ -138,7 +182,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--qd-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--legs", default="dd,qd,single",
+    ap.add_argument("--legs", default="dd,qd,single,sparse512",
                     help="comma list of dd (the reported line), qd, single; profiling runs use one")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -212,6 +256,7 @@ def main() -> int:
             "pct_fp64_peak": 100.0 * qd["flops"]["total"] * qd["B"] /
             (qd["ms_per_step"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS},
         "single_path_us_per_newton_step": None if single is None else single["ms_per_step"] * 1e3,
+        "sparse512": r.get("sparse512"),
     }
     if rank == 0:
         print(json.dumps(line), flush=True)

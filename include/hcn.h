@@ -107,8 +107,8 @@ int hcn_sys_degrees(hcn_sys sys, int32_t *degrees);
 size_t hcn_eval_ws_bytes(hcn_sys sys, int B);
 
 /* x_dev [B][n][2][P] -> f_dev [B][N][2][P] and J_dev [B][n][N][2][P]
- * (column-major: J[k][i] = df_i/dx_k).  J_dev may be NULL (values only is
- * not cheaper; the entry exists for symmetry).  ws_dev: hcn_eval_ws_bytes()
+ * (column-major: J[k][i] = df_i/dx_k).  J_dev may be NULL: then only the
+ * values are formed (products without their gradients).  ws_dev: hcn_eval_ws_bytes()
  * bytes of device memory, or NULL to let the call allocate and free it on
  * the stream. */
 int hcn_eval_jac(hcn_sys sys, int B, const double *x_dev, double *f_dev,
@@ -183,6 +183,18 @@ int hcn_newton(hcn_sys sys, const double *gamma, int relax_k, int B,
                const double *t_dev, double *x_dev, const hcn_newton_params *prm,
                double *norms_dev, int32_t *status_dev, int32_t *iters_dev,
                void *ws_dev, size_t ws_bytes, void *stream);
+
+/* Mixed precision: Fig. 2 where each iteration evaluates the residual h(x)
+ * in DD/QD (values only), takes its rounding to FP64 as right-hand side,
+ * forms the Jacobian in FP64 at the leading limbs of x, solves by MGS in
+ * FP64 and adds the FP64 correction to x in DD/QD; the iteration reaches
+ * full DD/QD accuracy while kappa(J) 2^-53 < 1.  Arguments, tests and outputs
+ * as hcn_newton; workspace from hcn_newton_mixed_ws_bytes. */
+size_t hcn_newton_mixed_ws_bytes(hcn_sys sys, int B);
+int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B,
+                     const double *t_dev, double *x_dev, const hcn_newton_params *prm,
+                     double *norms_dev, int32_t *status_dev, int32_t *iters_dev,
+                     void *ws_dev, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------------------
  * Path tracking (Fig. 3 with the step bounds of equation (4)), the step

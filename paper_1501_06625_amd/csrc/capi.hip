@@ -79,7 +79,7 @@ int g_mgs_variant = 0;  // 0 auto, 1 workgroup per problem, 2 right-looking, 3 c
 // choose and launch the MGS variant for B problems of size N x n
 int enqueue_mgs(int P, const MgsArgs &a, int *ints, hipStream_t s) {
     int v = g_mgs_variant;
-    if (v == 0) v = (a.n >= 160 && a.B <= 4) ? 3 : 1;
+    if (v == 0) v = (a.n >= 160 && a.B <= 4) ? 2 : 1;
     if (v == 1) return launch_mgs(P, a, s);
     return launch_mgs_big(P, a, v, ints, s);
 }
@@ -327,7 +327,7 @@ template <class C>
 EvalWs carve_eval(C &c, const SysView &v, int B) {
     EvalWs w;
     w.scratch = c.template take<double>((size_t)B * v.nslots * 2 * v.P);
-    w.norm_part = c.template take<double>((size_t)B * sum_nparts(v));
+    w.norm_part = c.template take<double>((size_t)B * sum_nparts(v, 1));
     return w;
 }
 
@@ -371,16 +371,53 @@ TrackWs carve_track(C &c, const SysView &v, int B) {
     return w;
 }
 
+MonArgs mon_args(const SysView &v, int B, const double *x, double *scratch, int RP,
+                 const PathState *st, int values_only) {
+    MonArgs m = {};
+    m.s = v;
+    m.B = B;
+    m.x = x;
+    m.x_pstride = (long)v.n * 2 * v.P;
+    m.xP = v.P;
+    m.scratch = scratch;
+    m.sc_pstride = (long)v.nslots * 2 * RP;
+    m.st = st;
+    m.values_only = values_only;
+    return m;
+}
+
+SumArgs sum_args(const SysView &v, int B, const double *scratch, int RP, const double *x,
+                 const Homotopy &hom, const PathState *st) {
+    SumArgs a = {};
+    a.s = v;
+    a.B = B;
+    a.scratch = scratch;
+    a.sc_pstride = (long)v.nslots * 2 * RP;
+    a.x = x;
+    a.x_pstride = (long)v.n * 2 * v.P;
+    a.xP = v.P;
+    a.hom = hom;
+    a.jac = 1;
+    a.st = st;
+    return a;
+}
+
 // evaluation of f (or h) and J into the augmented [J | -h] of the Newton
 // workspace, with the residual norm parts
 int enqueue_eval_aug(const SysView &v, int B, const double *x, const Homotopy &hom,
                      const NewtonWs &w, const PathState *st, hipStream_t s) {
     const long W = 2 * v.P;
-    int e = launch_mon(v.P, v, B, x, v.n * W, w.ev.scratch, (long)v.nslots * W, st, s);
+    int e = launch_mon(v.P, mon_args(v, B, x, w.ev.scratch, v.P, st, 0), s);
     if (e) return dev_fail(e, "evaluation launch");
-    e = launch_sum(v.P, v, B, w.ev.scratch, (long)v.nslots * W, x, v.n * W, hom, w.Jaug,
-                   v.N * W, (long)(v.n + 1) * v.N * W, w.Jaug + (size_t)v.n * v.N * W,
-                   (long)(v.n + 1) * v.N * W, 1, w.ev.norm_part, st, s);
+    SumArgs a = sum_args(v, B, w.ev.scratch, v.P, x, hom, st);
+    a.J = w.Jaug;
+    a.J_cstride = v.N * W;
+    a.J_pstride = (long)(v.n + 1) * v.N * W;
+    a.f = w.Jaug + (size_t)v.n * v.N * W;
+    a.f_pstride = (long)(v.n + 1) * v.N * W;
+    a.f_neg = 1;
+    a.norm_part = w.ev.norm_part;
+    e = launch_sum(v.P, a, s);
     if (e) return dev_fail(e, "summation launch");
     return HCN_OK;
 }
@@ -405,7 +442,7 @@ MgsArgs newton_mgs_args(const SysView &v, int B, const NewtonWs &w, double *x, i
     a.x = x;
     a.x_pstride = v.n * W;
     a.norm_part = w.ev.norm_part;
-    a.nparts = sum_nparts(v);
+    a.nparts = sum_nparts(v, 1);
     a.st = w.st;
     return a;
 }
@@ -419,6 +456,7 @@ int make_homotopy(const SysView &v, const double *gamma, int relax_k, const doub
     if (!t) return fail(HCN_EINVAL, "homotopy needs a device array of t values");
     hom.on = 1;
     hom.relax_k = relax_k;
+    hom.gP = v.P;
     std::memcpy(hom.gamma, gamma, sizeof(double) * 2 * v.P);
     hom.t = t;
     return HCN_OK;
@@ -449,12 +487,18 @@ int hcn_eval_jac(hcn_sys sys, int B, const double *x, double *f, double *J, void
     Carver c(wsp.ptr);
     EvalWs w = carve_eval(c, v, B);
     const long W = 2 * v.P;
-    int e = launch_mon(v.P, v, B, x, v.n * W, w.scratch, (long)v.nslots * W, nullptr, s);
+    int e = launch_mon(v.P, mon_args(v, B, x, w.scratch, v.P, nullptr, J ? 0 : 1), s);
     if (e) return dev_fail(e, "hcn_eval_jac: evaluation launch");
     Homotopy hom;
     std::memset(&hom, 0, sizeof hom);
-    e = launch_sum(v.P, v, B, w.scratch, (long)v.nslots * W, x, v.n * W, hom, J, v.N * W,
-                   (long)v.n * v.N * W, f, v.N * W, 0, nullptr, nullptr, s);
+    SumArgs a = sum_args(v, B, w.scratch, v.P, x, hom, nullptr);
+    a.jac = J ? 1 : 0;
+    a.J = J;
+    a.J_cstride = v.N * W;
+    a.J_pstride = (long)v.n * v.N * W;
+    a.f = f;
+    a.f_pstride = v.N * W;
+    e = launch_sum(v.P, a, s);
     if (e) return dev_fail(e, "hcn_eval_jac: summation launch");
     return HCN_OK;
 }
@@ -661,6 +705,120 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B, const 
                   done_steps);
     (void)hipHostFree(host_count);
     return rc;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct MixedWs {
+    double *sc_ext;    // values of the monomials in DD/QD
+    double *np;        // residual norm parts
+    double *sc64;      // values and partials in FP64
+    double *J64;       // [B][n+1][N][2]: FP64 Jacobian and rounded -h
+    double *R64, *inv64, *dx64;
+    PathState *st;
+    int *ints;
+};
+
+template <class C>
+MixedWs carve_mixed(C &c, const SysView &v, int B) {
+    MixedWs w;
+    w.sc_ext = c.template take<double>((size_t)B * v.nslots * 2 * v.P);
+    w.np = c.template take<double>((size_t)B * sum_nparts(v, 0));
+    w.sc64 = c.template take<double>((size_t)B * v.nslots * 2);
+    w.J64 = c.template take<double>((size_t)B * (v.n + 1) * v.N * 2);
+    w.R64 = c.template take<double>((size_t)B * (v.n + 1) * v.n * 2);
+    w.inv64 = c.template take<double>((size_t)B * v.n);
+    w.dx64 = c.template take<double>((size_t)B * v.n * 2);
+    w.st = c.template take<PathState>((size_t)B);
+    w.ints = c.template take<int>((size_t)2 * B + 1);
+    return w;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hcn_newton_mixed_ws_bytes(hcn_sys sys, int B) {
+    if (!sys || B < 0) return 0;
+    Carver c(nullptr);
+    carve_mixed(c, sys->v, B);
+    return c.off;
+}
+
+int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B, const double *t,
+                     double *x, const hcn_newton_params *prm, double *norms, int32_t *status,
+                     int32_t *iters, void *ws, size_t ws_bytes, void *stream) {
+    if (!sys || !prm) return fail(HCN_EINVAL, "hcn_newton_mixed: NULL system or parameters");
+    if (B < 0) return fail(HCN_EINVAL, "hcn_newton_mixed: negative batch");
+    if (prm->max_iter < 0 || prm->max_iter > 1000)
+        return fail(HCN_EINVAL, "hcn_newton_mixed: max_iter out of 0..1000");
+    if (B == 0) return HCN_OK;
+    if (!x) return fail(HCN_EINVAL, "hcn_newton_mixed: NULL x");
+    const SysView &v = sys->v;
+    Homotopy hom;
+    int rc = make_homotopy(v, gamma, relax_k, t, hom);
+    if (rc) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Workspace wsp;
+    rc = wsp.acquire(ws, ws_bytes, hcn_newton_mixed_ws_bytes(sys, B), s);
+    if (rc) return rc;
+    Carver c(wsp.ptr);
+    MixedWs w = carve_mixed(c, v, B);
+    int e = launch_newton_init(B, w.st, *prm, s);
+    if (e) return dev_fail(e, "hcn_newton_mixed: init launch");
+    const long colN = (long)v.N * 2;
+    MgsArgs a = {};
+    a.B = B;
+    a.N = v.N;
+    a.n = v.n;
+    a.mode = MGS_MIXED_SOLVE;
+    a.A = w.J64;
+    a.A_cstride = colN;
+    a.A_pstride = (long)(v.n + 1) * colN;
+    a.R = w.R64;
+    a.R_pstride = (long)(v.n + 1) * v.n * 2;
+    a.inv = w.inv64;
+    a.inv_pstride = v.n;
+    a.dx = w.dx64;
+    a.dx_pstride = (long)v.n * 2;
+    a.x = x;
+    a.x_pstride = (long)v.n * 2 * v.P;
+    a.norm_part = w.np;
+    a.nparts = sum_nparts(v, 0);
+    a.st = w.st;
+    for (int it = 0; it < prm->max_iter; ++it) {
+        // residual in extended precision; its rounding is the right-hand side
+        e = launch_mon(v.P, mon_args(v, B, x, w.sc_ext, v.P, w.st, 1), s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: residual launch");
+        SumArgs sr = sum_args(v, B, w.sc_ext, v.P, x, hom, w.st);
+        sr.jac = 0;
+        sr.f = w.J64 + (size_t)v.n * colN;
+        sr.f_pstride = (long)(v.n + 1) * colN;
+        sr.f_neg = 1;
+        sr.f_lead_only = 1;
+        sr.norm_part = w.np;
+        e = launch_sum(v.P, sr, s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: residual sum launch");
+        e = launch_fig2_pre(a, s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: test launch");
+        // the Jacobian in FP64 at the leading limbs of x
+        e = launch_mon(1, mon_args(v, B, x, w.sc64, 1, w.st, 0), s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: Jacobian launch");
+        SumArgs sj = sum_args(v, B, w.sc64, 1, x, hom, w.st);
+        sj.J = w.J64;
+        sj.J_cstride = colN;
+        sj.J_pstride = (long)(v.n + 1) * colN;
+        e = launch_sum(1, sj, s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: Jacobian sum launch");
+        e = enqueue_mgs(1, a, w.ints, s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: solve launch");
+        e = launch_mixed_update(v.P, a, s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: update launch");
+    }
+    e = launch_newton_finish(B, w.st, norms, status, iters, s);
+    return dev_fail(e, "hcn_newton_mixed: finish launch");
 }
 
 int hcn_set_mgs_variant(int variant) {

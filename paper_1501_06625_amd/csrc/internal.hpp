@@ -43,7 +43,8 @@ struct SysView {
 struct Homotopy {
     int on;            // 0: plain f
     int relax_k;
-    double gamma[8];   // [2][P]
+    int gP;            // limbs of gamma
+    double gamma[8];   // [2][gP]
     const double *t;   // device [B]
 };
 
@@ -61,7 +62,9 @@ struct PathState {
 enum { PHASE_TRACK = 0, PHASE_REFINE = 1, PHASE_DONE = 2 };
 enum { C_RUNNING = 100 };
 
-enum MgsMode { MGS_SOLVE = 0, MGS_NEWTON_STEP = 1, MGS_NEWTON_FIG2 = 2 };
+// MGS_MIXED_SOLVE: solve only (no update), for problems whose corrector is
+// still active; a singular matrix ends the corrector
+enum MgsMode { MGS_SOLVE = 0, MGS_NEWTON_STEP = 1, MGS_NEWTON_FIG2 = 2, MGS_MIXED_SOLVE = 3 };
 
 struct MgsArgs {
     int B, N, n, mode;
@@ -84,21 +87,56 @@ struct MgsArgs {
     PathState *st;      // Fig. 2 mode
 };
 
-// launchers (return hipError_t as int)
-int launch_mon(int P, const SysView &s, int B, const double *x, long x_pstride,
-               double *scratch, long sc_pstride, const PathState *st,
-               hipStream_t stream);
-int launch_sum(int P, const SysView &s, int B, const double *scratch, long sc_pstride,
-               const double *x, long x_pstride, const Homotopy &hom, double *J,
-               long J_cstride, long J_pstride, double *f, long f_pstride, int f_neg,
-               double *norm_part, const PathState *st, hipStream_t stream);
-int sum_nparts(const SysView &s);
-int launch_mgs(int P, const MgsArgs &a, hipStream_t stream);
+// monomial values and partials of B points (compute precision: 1, 2 or 4
+// limbs, at most the storage limbs of x and of the coefficients)
+struct MonArgs {
+    SysView s;
+    int B;
+    const double *x;     // [B] points, x_pstride doubles apart, xP limbs
+    long x_pstride;
+    int xP;
+    double *scratch;     // [B] nslots complex numbers in compute precision
+    long sc_pstride;
+    const PathState *st; // skip paths whose corrector is idle (or NULL)
+    int values_only;
+};
+
+// sums of the slots into f (or -h) and the column-major Jacobian
+struct SumArgs {
+    SysView s;
+    int B;
+    const double *scratch;
+    long sc_pstride;
+    const double *x;     // for the start-system terms of the homotopy
+    long x_pstride;
+    int xP;
+    Homotopy hom;
+    int jac;             // 0: values only
+    double *J;           // entry (k, i) of path b at J + b*J_pstride + k*J_cstride + i*2P
+    long J_cstride, J_pstride;
+    double *f;
+    long f_pstride;
+    int f_neg;           // store -f
+    int f_lead_only;     // store the leading limbs only ([2] doubles per entry)
+    double *norm_part;   // [B][nparts] block maxima of the leading limbs, or NULL
+    const PathState *st;
+};
+
+// launchers (return hipError_t as int); RP = limbs of the compute precision
+int launch_mon(int RP, const MonArgs &a, hipStream_t stream);
+int launch_sum(int RP, const SumArgs &a, hipStream_t stream);
+int sum_nparts(const SysView &s, int jac);
+int launch_mgs(int RP, const MgsArgs &a, hipStream_t stream);
 // multi-workgroup MGS for large single problems: variant 2 right-looking
 // (one launch per column step), 3 column-resident (cooperative); ints_dev
 // holds 2B+1 ints of workspace
 int launch_mgs_big(int P, const MgsArgs &a, int variant, int *ints_dev, hipStream_t stream);
 size_t mgs_res_lds(int N, int n, int P);
+// Fig. 2 tests before a solve, one lane per problem (norm parts of a.norm_part)
+int launch_fig2_pre(const MgsArgs &a, hipStream_t stream);
+// mixed precision: x (xP limbs) += dx (double), the update norm and the Fig. 2
+// tests after a solve
+int launch_mixed_update(int xP, const MgsArgs &a, hipStream_t stream);
 int launch_elementwise(int op, int P, int count, const double *a, const double *b,
                        double *out, hipStream_t stream);
 

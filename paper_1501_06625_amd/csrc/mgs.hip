@@ -62,9 +62,9 @@ __global__ __launch_bounds__(MGS_THREADS) void k_mgs(MgsArgs a) {
     __shared__ double s_inv[4];
 
     // ---- Fig. 2 tests before the solve (residual norm vs previous, tolerance)
-    if (a.mode == MGS_NEWTON_FIG2) {
+    if (a.mode == MGS_NEWTON_FIG2 || a.mode == MGS_MIXED_SOLVE) {
         // one lane reads and decides; the others learn it through LDS
-        if (tid == 0) s_flag = fig2_decide(a, b);
+        if (tid == 0) s_flag = a.mode == MGS_NEWTON_FIG2 ? fig2_decide(a, b) : !a.st[b].c_active;
         __syncthreads();
         if (s_flag) return;
     }
@@ -138,7 +138,9 @@ __global__ __launch_bounds__(MGS_THREADS) void k_mgs(MgsArgs a) {
 int launch_mgs(int P, const MgsArgs &a, hipStream_t stream) {
     if (a.B == 0) return 0;
     ProfScope prof("mgs", stream);
-    if (P == 2)
+    if (P == 1)
+        hipLaunchKernelGGL(k_mgs<double>, dim3(a.B), dim3(MGS_THREADS), 0, stream, a);
+    else if (P == 2)
         hipLaunchKernelGGL(k_mgs<dd>, dim3(a.B), dim3(MGS_THREADS), 0, stream, a);
     else
         hipLaunchKernelGGL(k_mgs<qd>, dim3(a.B), dim3(MGS_THREADS), 0, stream, a);

@@ -150,7 +150,7 @@ HCN_DEV double *col_ptr(const MgsArgs &a, int b, int j) {
 }
 
 HCN_DEV bool problem_live(const MgsArgs &a, int b) {
-    return a.mode != MGS_NEWTON_FIG2 || a.st[b].c_active;
+    return (a.mode != MGS_NEWTON_FIG2 && a.mode != MGS_MIXED_SOLVE) || a.st[b].c_active;
 }
 
 // ---------------------------------------------------------------------------
@@ -351,7 +351,14 @@ static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s)
 int launch_mgs_big(int P, const MgsArgs &a, int variant, int *ints, hipStream_t s) {
     if (a.B == 0) return 0;
     if (variant == 3 && mgs_res_lds(a.N, a.n, P) == 0) variant = 2;
+    if (P == 1) return launch_big_t<double>(a, variant, ints, s);
     return P == 2 ? launch_big_t<dd>(a, variant, ints, s) : launch_big_t<qd>(a, variant, ints, s);
+}
+
+int launch_fig2_pre(const MgsArgs &a, hipStream_t s) {
+    if (a.B == 0) return 0;
+    hipLaunchKernelGGL(k_fig2_pre, dim3((a.B + 255) / 256), dim3(256), 0, s, a);
+    return (int)hipGetLastError();
 }
 
 }  // namespace hcn

@@ -50,7 +50,7 @@ HCN_DEV void mgs_epilogue(const MgsArgs &a, int b, bool singular) {
     if (singular) {
         if (tid == 0) {
             if (a.status) a.status[b] = HCN_ESINGULAR;
-            if (a.mode == MGS_NEWTON_FIG2) {
+            if (a.mode == MGS_NEWTON_FIG2 || a.mode == MGS_MIXED_SOLVE) {
                 a.st[b].c_status = HCN_ESINGULAR;
                 a.st[b].c_active = 0;
             }
@@ -83,7 +83,7 @@ HCN_DEV void mgs_epilogue(const MgsArgs &a, int b, bool singular) {
         __syncthreads();
     }
 
-    if (a.mode == MGS_SOLVE) {
+    if (a.mode == MGS_SOLVE || a.mode == MGS_MIXED_SOLVE) {
         if (tid == 0 && a.status) a.status[b] = HCN_OK;
         return;
     }

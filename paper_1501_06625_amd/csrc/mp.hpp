@@ -300,24 +300,46 @@ HCN_DEV qd sqrt(const qd &a) {
 HCN_DEV double lead(const qd &a) { return a.c0; }
 
 // ---------------------------------------------------------------------------
+// plain double (the FP64 Jacobian and QR of the mixed-precision Newton step)
+// ---------------------------------------------------------------------------
+
+HCN_DEV double add(double a, double b) { return a + b; }
+HCN_DEV double sub(double a, double b) { return a - b; }
+HCN_DEV double mul(double a, double b) { return a * b; }
+HCN_DEV double mul_d(double a, double b) { return a * b; }
+HCN_DEV double div(double a, double b) { return a / b; }
+HCN_DEV double sqrt(double a) { return ::sqrt(a); }
+HCN_DEV double lead(double a) { return a; }
+
+// ---------------------------------------------------------------------------
 // precision traits: limbs and interleaved loads / stores
 // ---------------------------------------------------------------------------
 
 template <class R> struct limbs;
+template <> struct limbs<double> { static constexpr int P = 1; };
 template <> struct limbs<dd> { static constexpr int P = 2; };
 template <> struct limbs<qd> { static constexpr int P = 4; };
 
 template <class R> HCN_DEV R rmake(double h);
+template <> HCN_DEV double rmake<double>(double h) { return h; }
 template <> HCN_DEV dd rmake<dd>(double h) { return dd_make(h); }
 template <> HCN_DEV qd rmake<qd>(double h) { return qd_make(h); }
 
+HCN_DEV void rload(const double *p, double &r) { r = p[0]; }
 HCN_DEV void rload(const double *p, dd &r) { r = dd{p[0], p[1]}; }
 HCN_DEV void rload(const double *p, qd &r) { r = qd{p[0], p[1], p[2], p[3]}; }
+HCN_DEV void rstore(double *p, double r) { p[0] = r; }
 HCN_DEV void rstore(double *p, const dd &r) { p[0] = r.hi; p[1] = r.lo; }
 HCN_DEV void rstore(double *p, const qd &r) { p[0] = r.c0; p[1] = r.c1; p[2] = r.c2; p[3] = r.c3; }
 
+HCN_DEV bool rfinite(double a) { return __builtin_isfinite(a); }
 HCN_DEV bool rfinite(const dd &a) { return __builtin_isfinite(a.hi); }
 HCN_DEV bool rfinite(const qd &a) { return __builtin_isfinite(a.c0); }
+
+// widen a double-precision value to R (exact)
+HCN_DEV void rwiden(double a, double &r) { r = a; }
+HCN_DEV void rwiden(double a, dd &r) { r = dd{a, 0.0}; }
+HCN_DEV void rwiden(double a, qd &r) { r = qd{a, 0.0, 0.0, 0.0}; }
 
 // ---------------------------------------------------------------------------
 // complex numbers over R
@@ -335,6 +357,22 @@ template <class R> HCN_DEV cx<R> cload(const double *p) {
     cx<R> z;
     rload(p, z.re);
     rload(p + P, z.im);
+    return z;
+}
+
+// a complex stored with Ps limbs per part, read in precision R (the leading
+// limbs when R is narrower; Ps must be >= the limbs of R)
+template <class R> HCN_DEV cx<R> cload_s(const double *p, int Ps) {
+    cx<R> z;
+    rload(p, z.re);
+    rload(p + Ps, z.im);
+    return z;
+}
+
+template <class R> HCN_DEV cx<R> cwiden(const cx<double> &a) {
+    cx<R> z;
+    rwiden(a.re, z.re);
+    rwiden(a.im, z.im);
     return z;
 }
 

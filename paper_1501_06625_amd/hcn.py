@@ -63,7 +63,7 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_sys_degrees", "hcn_eval_ws_bytes", "hcn_eval_jac", "hcn_mgs_ws_bytes",
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
-           "hcn_set_mgs_variant",
+           "hcn_set_mgs_variant", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
            "hcn_profile_reset", "hcn_profile_query"]
 
 
@@ -95,6 +95,9 @@ def _load():
     lib.hcn_elementwise.argtypes = [ci, ci, ci, vp, vp, vp, vp]
     lib.hcn_profile_enable.argtypes = [ci]
     lib.hcn_set_mgs_variant.argtypes = [ci]
+    lib.hcn_newton_mixed_ws_bytes.argtypes = [vp, ci]
+    lib.hcn_newton_mixed_ws_bytes.restype = sz
+    lib.hcn_newton_mixed.argtypes = lib.hcn_newton.argtypes
     lib.hcn_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(cd),
                                       ctypes.POINTER(ctypes.c_int64)]
     return lib
@@ -258,19 +261,24 @@ def newton_ws(sys: System, B: int, device=None) -> torch.Tensor:
 
 def newton(sys: System, x: torch.Tensor, gamma=None, t: Optional[torch.Tensor] = None,
            relax_k: int = 1, max_iter: int = 3, tol_res: float = 1e-12, tol_dx: float = 1e-12,
-           max_eq_val: float = 1.0):
-    """Fig. 2 corrector in place on x; returns (status [B], iters [B], norms [B][2])."""
+           max_eq_val: float = 1.0, mixed: bool = False, ws: Optional[torch.Tensor] = None):
+    """Fig. 2 corrector in place on x; returns (status [B], iters [B], norms [B][2]).
+    mixed=True: FP64 Jacobian and solve, residual and update in DD/QD."""
     xb, batched = _batched(x, 3)
+    if not xb.is_contiguous():
+        raise ValueError("x must be contiguous (updated in place)")
     B = xb.shape[0]
     norms = torch.empty((B, 2), dtype=torch.float64, device=x.device)
     status = torch.empty(B, dtype=torch.int32, device=x.device)
     iters = torch.empty(B, dtype=torch.int32, device=x.device)
     g, gp = _gamma_arg(gamma, sys.P)
     prm = _NewtonParams(max_iter, tol_res, tol_dx, max_eq_val)
-    ws = _workspace(_lib.hcn_newton_ws_bytes(sys.handle, B), x.device)
-    _check(_lib.hcn_newton(sys.handle, gp, relax_k, B, _ptr(t), _ptr(xb), ctypes.byref(prm),
-                           _ptr(norms), _ptr(status), _ptr(iters), _ptr(ws), ws.numel(),
-                           _stream()))
+    need = (_lib.hcn_newton_mixed_ws_bytes if mixed else _lib.hcn_newton_ws_bytes)(sys.handle, B)
+    if ws is None or ws.numel() < need:
+        ws = _workspace(need, x.device)
+    fn = _lib.hcn_newton_mixed if mixed else _lib.hcn_newton
+    _check(fn(sys.handle, gp, relax_k, B, _ptr(t), _ptr(xb), ctypes.byref(prm),
+              _ptr(norms), _ptr(status), _ptr(iters), _ptr(ws), ws.numel(), _stream()))
     if not batched:
         return status[0], iters[0], norms[0]
     return status, iters, norms

@@ -300,6 +300,27 @@ def batch_systems(count: int = 64, seed: int = 0, P: int = DD,
     return out
 
 
+def with_root_at_ones(sys: PolySystem) -> PolySystem:
+    """Append to every equation the constant term minus the sum of its
+    coefficients, so that x = (1, ..., 1) is a root (the sum is formed at
+    320 bits and rounded to the system's limbs)."""
+    P = sys.P
+    eqs, coefs = [], []
+    for i in range(sys.N):
+        mons = []
+        with mpmath.workprec(_MP_PREC):
+            acc = mpmath.mpc(0)
+            for m, mon in sys.monomials(i):
+                mons.append(mon)
+                coefs.append(np.asarray(sys.coef[m]))
+                acc += limbs_to_complex(sys.coef[m])
+            mons.append([])
+            coefs.append(complex_to_limbs(-acc, P))
+        eqs.append(mons)
+    return system_from_monomials(sys.N, sys.n, P, eqs, np.asarray(coefs),
+                                 name=sys.name + "+root1")
+
+
 def diagonal_power_system(cs: np.ndarray, d: int, P: int) -> PolySystem:
     """f_i = x_i^d - c_i, i = 0..n-1 (coefficient of x_i^d is 1); cs: [n][2][P]."""
     n = cs.shape[0]

@@ -456,3 +456,54 @@ def test_newton_step_sparse512_vs_oracle(H):
     tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
     for v in (1, 3):
         assert np.abs(limb_diff(out[v], xo)).max() <= tol * no[1], v
+
+
+# ---------------------------------------------------------------------------
+# mixed precision: FP64 Jacobian and solve, DD/QD residual and update
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_mixed_newton_reaches_extended_accuracy(H, P):
+    """From near a planted root, the mixed-precision corrector reaches the
+    root to DD/QD accuracy (checked in mpmath) and agrees with plain DD/QD
+    Newton to the same tolerance."""
+    rng = S.rng_for(3, 70 + P)
+    base = S.random_system(rng, 12, 12, 10, (3, 6), (1, 2, 3), P)
+    root = S.random_unit_point(rng, 12, P)
+    f = M.planted_constant_terms(base, root)
+    B = 4
+    x0 = np.stack([root.copy() for _ in range(B)])
+    x0[:, :, 0, 0] += 1e-6 * rng.standard_normal((B, 12))
+    sysd = H.System(f)
+    tol = GATE[P]
+    xm = dev(x0)
+    st_m, it_m, nm = H.newton(sysd, xm, max_iter=30, tol_res=tol, tol_dx=tol, max_eq_val=1.0,
+                              mixed=True)
+    xp = dev(x0)
+    st_p, it_p, npn = H.newton(sysd, xp, max_iter=10, tol_res=tol, tol_dx=tol, max_eq_val=1.0)
+    st_m, it_m, st_p = host(st_m), host(it_m), host(st_p)
+    assert np.all(st_m == 0), st_m
+    assert np.all(st_p == 0), st_p
+    xm, xp = host(xm), host(xp)
+    for q in range(B):
+        err = max(abs(M.mp_complex(xm[q, i]) - M.mp_complex(root[i])) for i in range(12))
+        assert err <= 100 * tol
+        assert np.abs(limb_diff(xm[q], xp[q])).max() <= 100 * tol
+        # residual at the result, at 320 bits
+        fv, _ = M.eval_system(f, M.vec(xm[q]))
+        assert max(abs(v) for v in fv) <= 100 * tol
+
+
+def test_mixed_newton_fig2_branches(H):
+    P = 2
+    f = S.random_system(S.rng_for(3, 90), 6, 6, 5, (2, 3), (1, 2), P, const_term=True)
+    x = random_points(np.random.default_rng(4), 2, 6, P)
+    sysd = H.System(f)
+    xd = dev(x)
+    st, it, nr = H.newton(sysd, xd, max_eq_val=1e-30, mixed=True)
+    assert np.all(host(st) == H.DIVERGED) and np.all(host(it) == 1)
+    assert _bitwise_equal(host(xd), x)
+    xd = dev(x)
+    st, it, nr = H.newton(sysd, xd, max_iter=1, tol_res=1e-300, tol_dx=1e-300,
+                          max_eq_val=1e300, mixed=True)
+    assert np.all(host(st) == H.NOT_CONVERGED) and np.all(host(it) == 1)
