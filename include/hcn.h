@@ -145,6 +145,18 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A_dev, double *b_dev,
  * columns do not fit in LDS. */
 int hcn_set_mgs_variant(int variant);
 
+/* Kernel-variant table used by the one-workgroup MGS: lane-group width
+ * (8, 16 or 32 lanes per column) and LDS staging (0/1) per precision P
+ * (1 = the FP64 solve of the mixed-precision step, 2, 4) and row count N
+ * (bucketed to the next power of two >= 8).  Defaults: 16, LDS on.  The
+ * choice depends only on (P, N), so a problem's result does not depend on
+ * the batch it is solved in.  save/load: text, one "P N group lds" line per
+ * entry.  hcn_autotune (batch section) fills the table by timing. */
+int hcn_tune_set(int P, int N, int mgs_group, int mgs_lds);
+int hcn_tune_get(int P, int N, int *mgs_group, int *mgs_lds);
+int hcn_tune_save(const char *path);
+int hcn_tune_load(const char *path);
+
 /* ------------------------------------------------------------------------
  * Newton's method (equation (2); Fig. 2).  The system is either f alone
  * (gamma == NULL) or the homotopy of equation (1),
@@ -236,6 +248,50 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B,
                     const double *x0_dev, const hcn_track_params *prm,
                     double *x_out_dev, hcn_path_result *results_dev,
                     void *ws_dev, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batches: a slot table of up to `capacity` paths of any number of systems
+ * of one precision, tracked together (Fig. 3 per path, the step size of
+ * each path its own).  Every kernel launch covers every occupied slot; the
+ * step is captured once into a HIP graph and replayed; the work lists are
+ * rebuilt when slots are added or released.  A path's arithmetic depends
+ * only on its own system, start point, gamma and the tuning table, so its
+ * result is bitwise the same alone and in any mix.  Sizing: every system
+ * added must have N == n <= max_n and at most max_nslots evaluation slots
+ * (hcn_sys_info); at most max_systems distinct systems per batch.
+ * --------------------------------------------------------------------- */
+
+typedef struct hcn_batch_s *hcn_batch;
+
+int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nslots,
+                     int max_systems, const hcn_track_params *prm, int relax_k);
+int hcn_batch_destroy(hcn_batch b);
+size_t hcn_batch_device_bytes(hcn_batch b);
+const char *hcn_batch_last_error(void);
+
+/* Occupy a free slot with a path of `sys` from x0_dev ([n][2][P], device;
+ * read by work enqueued on `stream`, keep it alive until then) with gamma
+ * (host [2][P]); the path starts at t = 0. */
+int hcn_batch_add(hcn_batch b, int slot, hcn_sys sys, const double *gamma,
+                  const double *x0_dev, void *stream);
+
+/* Free a slot (its result is no longer available). */
+int hcn_batch_release(hcn_batch b, int slot);
+
+/* Enqueue `steps` predictor-corrector steps of every unfinished path. */
+int hcn_batch_step(hcn_batch b, int steps, void *stream);
+
+/* Number of occupied, unfinished slots (>= 0) or an error; done_host (NULL
+ * or [capacity]) receives 1 for finished slots.  Waits for the stream. */
+int hcn_batch_poll(hcn_batch b, int32_t *done_host, void *stream);
+
+/* Result of a finished slot: x_out_dev ([n][2][P], device, or NULL) and
+ * *res_host (or NULL).  Waits for the stream when res_host is given. */
+int hcn_batch_result(hcn_batch b, int slot, double *x_out_dev, hcn_path_result *res_host,
+                     void *stream);
+
+/* Step every occupied slot to the end, polling after every `chunk` steps. */
+int hcn_batch_run(hcn_batch b, int chunk, void *stream);
 
 /* ------------------------------------------------------------------------
  * Elementwise arithmetic (the DD/QD layer itself, Section 3.1), for

@@ -1,0 +1,547 @@
+// batch.hip -- a slot table of paths of many systems (one precision), all
+// advanced together: every kernel launch covers every occupied slot, each
+// workgroup finding its path's system and workspace from the slot index.
+//
+// Per step: begin (one workgroup per slot: trial t, predictor), then
+// max_iter times { monomials (one workgroup per (slot, block of 256
+// monomials)), sums (one per (slot, block of 256 outputs)), MGS (one per
+// slot, one launch per lane-group width) }, then end (controller).  The
+// work lists are rebuilt on the host when slots are added or released; the
+// step is captured once into a HIP graph and replayed.  Each slot's
+// arithmetic depends only on its own system, point and tuning entry, so a
+// path gives the same bits alone and in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <vector>
+
+#include "eval_body.hpp"
+#include "internal.hpp"
+#include "mgs_common.hpp"
+#include "mp.hpp"
+#include "prof.hpp"
+#include "track_body.hpp"
+
+namespace hcn {
+
+struct BatchDev {
+    int P, max_n, max_nparts, relax_k;
+    const SysView *sys;   // registry
+    const int *slot_sys;  // [cap] registry index, -1 empty
+    const int *slot_lds;  // [cap] stage [A | b] in LDS
+    double *x, *x_acc, *x_prev, *x_out, *sc, *J, *R, *inv, *dx, *np, *t, *gamma;
+    PathState *st;
+    hcn_path_result *res;
+    long xs, scs, Js, Rs, invs, nps;
+    TrackArgs prm;
+};
+
+HCN_DEV TrackPath slot_path(const BatchDev &d, int slot) {
+    TrackPath p;
+    p.n = d.sys[d.slot_sys[slot]].n;
+    p.st = d.st + slot;
+    p.x = d.x + (size_t)slot * d.xs;
+    p.x_acc = d.x_acc + (size_t)slot * d.xs;
+    p.x_prev = d.x_prev + (size_t)slot * d.xs;
+    p.x_out = d.x_out + (size_t)slot * d.xs;
+    p.t = d.t + slot;
+    p.res = d.res + slot;
+    return p;
+}
+
+template <class R>
+__global__ void k_b_init(BatchDev d, int slot, const double *x0) {
+    track_init_one<R>(d.prm, slot_path(d, slot), x0);
+}
+
+template <class R>
+__global__ void k_b_begin(BatchDev d, const int *slots) {
+    track_begin_one<R>(d.prm, slot_path(d, slots[blockIdx.x]));
+}
+
+template <class R>
+__global__ void k_b_end(BatchDev d, const int *slots) {
+    track_end_one<R>(d.prm, slot_path(d, slots[blockIdx.x]));
+}
+
+template <class R, int KB, int MODE>
+__global__ __launch_bounds__(256) void k_b_mon(BatchDev d, const int2 *work) {
+    const int2 w = work[blockIdx.x];
+    const int slot = w.x;
+    if (!d.st[slot].c_active) return;
+    const SysView &s = d.sys[d.slot_sys[slot]];
+    const int m = w.y * 256 + threadIdx.x;
+    if (m >= s.nmon) return;
+    mon_one<R, KB, MODE>(s, m, d.x + (size_t)slot * d.xs, d.P, d.sc + (size_t)slot * d.scs);
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_b_sum(BatchDev d, const int2 *work) {
+    constexpr int W = 2 * limbs<R>::P;
+    __shared__ double red[256 / 64];
+    const int2 w = work[blockIdx.x];
+    const int slot = w.x;
+    if (!d.st[slot].c_active) return;
+    const SysView &s = d.sys[d.slot_sys[slot]];
+    double *J = d.J + (size_t)slot * d.Js;
+    SumOut o;
+    o.jac = 1;
+    o.J = J;
+    o.J_cstride = (long)s.N * W;
+    o.f = J + (size_t)s.n * s.N * W;
+    o.f_neg = 1;
+    o.f_lead_only = 0;
+    const long e = (long)w.y * 256 + threadIdx.x;
+    const double mx = sum_one<R>(s, e, d.sc + (size_t)slot * d.scs, d.x + (size_t)slot * d.xs, d.P,
+                                 1, d.relax_k, d.t[slot], d.gamma + (size_t)slot * W, d.P, o);
+    const double r = block_max(mx, red);
+    if (threadIdx.x == 0) d.np[(size_t)slot * d.nps + w.y] = r;
+}
+
+template <class R, int GRP>
+__global__ __launch_bounds__(MGS_THREADS) void k_b_mgs(BatchDev d, const int *slots) {
+    constexpr int W = 2 * limbs<R>::P;
+    const int slot = slots[blockIdx.x];
+    const SysView &s = d.sys[d.slot_sys[slot]];
+    MgsProblem p;
+    p.N = s.N;
+    p.n = s.n;
+    p.mode = MGS_NEWTON_FIG2;
+    p.lds = d.slot_lds[slot];
+    p.A = d.J + (size_t)slot * d.Js;
+    p.A_cstride = (long)s.N * W;
+    p.bcol = p.A + (size_t)s.n * s.N * W;
+    p.R = d.R + (size_t)slot * d.Rs;
+    p.inv = d.inv + (size_t)slot * d.invs;
+    p.dx = d.sc + (size_t)slot * d.scs;  // the scratch is free once the sums are formed
+    p.status = nullptr;
+    p.x = d.x + (size_t)slot * d.xs;
+    p.norm_part = d.np + (size_t)slot * d.nps;
+    p.nparts = (int)(((long)s.n * s.N + s.N + 255) / 256);
+    p.norms = nullptr;
+    p.st = d.st + slot;
+    mgs_wg<R, GRP>(p);
+}
+
+__global__ void k_b_flags(BatchDev d, int cap, int32_t *done, int32_t *running) {
+    __shared__ int red[256 / 64];
+    int c = 0;
+    for (int s = threadIdx.x; s < cap; s += blockDim.x) {
+        const bool occ = d.slot_sys[s] >= 0;
+        const bool fin = occ && d.st[s].phase == PHASE_DONE;
+        done[s] = fin ? 1 : 0;
+        c += (occ && !fin) ? 1 : 0;
+    }
+    for (int off = 32; off >= 1; off >>= 1) c += __shfl_xor(c, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += red[w];
+        *running = t;
+    }
+}
+
+}  // namespace hcn
+
+using namespace hcn;
+
+namespace {
+
+thread_local std::string g_berr;
+
+int bfail(int code, const char *msg) {
+    g_berr = msg;
+    return code;
+}
+
+size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int kbucket_b(int k) {
+    if (k <= 4) return 4;
+    if (k <= 8) return 8;
+    if (k <= 16) return 16;
+    if (k <= 32) return 32;
+    return 64;
+}
+
+}  // namespace
+
+struct hcn_batch_s {
+    int P = 2, cap = 0, max_n = 0, max_nslots = 0, max_sys = 0;
+    BatchDev d = {};
+    void *dmem = nullptr;
+    size_t bytes = 0;
+    // registry
+    std::vector<hcn_sys> systems;
+    std::vector<SysView> views;
+    SysView *d_sys = nullptr;
+    int kb = 4;
+    // slots
+    std::vector<int> slot_sys, slot_lds;
+    int *d_slot_sys = nullptr, *d_slot_lds = nullptr;
+    // work lists
+    int2 *d_mon = nullptr, *d_sum = nullptr;
+    int *d_slots = nullptr;
+    int n_mon = 0, n_sum = 0, n_slots = 0;
+    int grp_off[3] = {0, 0, 0}, grp_cnt[3] = {0, 0, 0};
+    size_t grp_lds[3] = {0, 0, 0};
+    long mon_cap = 0, sum_cap = 0;
+    int32_t *d_done = nullptr, *d_running = nullptr;
+    int32_t *h_running = nullptr, *h_done = nullptr;
+    bool dirty = true;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t exec_stream = nullptr;
+};
+
+extern "C" const char *hcn_batch_last_error(void) { return g_berr.c_str(); }
+
+namespace {
+
+template <class R>
+int enqueue_step(hcn_batch_s *b, hipStream_t s) {
+    const BatchDev &d = b->d;
+    if (b->n_slots == 0) return 0;
+    hipLaunchKernelGGL(k_b_begin<R>, dim3(b->n_slots), dim3(64), 0, s, d, b->d_slots);
+    constexpr bool isdd = limbs<R>::P == 2;
+    for (int it = 0; it < d.prm.max_iter; ++it) {
+        switch (b->kb) {
+            case 4: hipLaunchKernelGGL((k_b_mon<R, 4, isdd ? MON_FREG : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+            case 8: hipLaunchKernelGGL((k_b_mon<R, 8, isdd ? MON_FREG : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+            case 16: hipLaunchKernelGGL((k_b_mon<R, 16, isdd ? MON_FREG : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+            case 32: hipLaunchKernelGGL((k_b_mon<R, 32, MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+            default: hipLaunchKernelGGL((k_b_mon<R, 64, MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+        }
+        hipLaunchKernelGGL(k_b_sum<R>, dim3(b->n_sum), dim3(256), 0, s, d, b->d_sum);
+        const int grps[3] = {8, 16, 32};
+        for (int g = 0; g < 3; ++g) {
+            if (b->grp_cnt[g] == 0) continue;
+            const int *list = b->d_slots + b->grp_off[g];
+            const size_t lds = b->grp_lds[g];
+            switch (grps[g]) {
+                case 8: hipLaunchKernelGGL((k_b_mgs<R, 8>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
+                case 16: hipLaunchKernelGGL((k_b_mgs<R, 16>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
+                default: hipLaunchKernelGGL((k_b_mgs<R, 32>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_b_end<R>, dim3(b->n_slots), dim3(64), 0, s, d, b->d_slots);
+    return (int)hipGetLastError();
+}
+
+template <class R>
+void set_lds_attributes() {
+    const int lim = (int)mgs_lds_limit();
+    (void)hipFuncSetAttribute((const void *)k_b_mgs<R, 8>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void *)k_b_mgs<R, 16>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    (void)hipFuncSetAttribute((const void *)k_b_mgs<R, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+}
+
+// work lists from the occupied slots; slots grouped by MGS lane-group width
+int rebuild(hcn_batch_s *b) {
+    std::vector<int2> mon, sum;
+    std::vector<int> lists[3];
+    const int grps[3] = {8, 16, 32};
+    size_t lds_need[3] = {0, 0, 0};
+    for (int s = 0; s < b->cap; ++s) {
+        if (b->slot_sys[s] < 0) continue;
+        const SysView &v = b->views[b->slot_sys[s]];
+        const int mb = (v.nmon + 255) / 256;
+        for (int q = 0; q < mb; ++q) mon.push_back(make_int2(s, q));
+        const int sb = sum_nparts(v, 1);
+        for (int q = 0; q < sb; ++q) sum.push_back(make_int2(s, q));
+        const int grp = tune_mgs_group(b->P, v.N);
+        const int g = grp == 8 ? 0 : grp == 32 ? 2 : 1;
+        lists[g].push_back(s);
+        const size_t bytes = mgs_lds_bytes(v.N, v.n, b->P);
+        const int lds = (bytes <= mgs_lds_limit() && tune_mgs_lds(b->P, v.N)) ? 1 : 0;
+        b->slot_lds[s] = lds;
+        if (lds) lds_need[g] = std::max(lds_need[g], bytes);
+        (void)grps;
+    }
+    std::vector<int> slots;
+    for (int g = 0; g < 3; ++g) {
+        b->grp_off[g] = (int)slots.size();
+        b->grp_cnt[g] = (int)lists[g].size();
+        b->grp_lds[g] = lds_need[g];
+        slots.insert(slots.end(), lists[g].begin(), lists[g].end());
+    }
+    b->n_mon = (int)mon.size();
+    b->n_sum = (int)sum.size();
+    b->n_slots = (int)slots.size();
+    if ((long)mon.size() > b->mon_cap || (long)sum.size() > b->sum_cap)
+        return bfail(HCN_EINVAL, "hcn_batch: work list exceeds its capacity");
+    hipError_t e = hipSuccess;
+    if (!mon.empty()) e = hipMemcpy(b->d_mon, mon.data(), mon.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (!e && !sum.empty()) e = hipMemcpy(b->d_sum, sum.data(), sum.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (!e && !slots.empty()) e = hipMemcpy(b->d_slots, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(b->d_slot_sys, b->slot_sys.data(), b->cap * sizeof(int), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy(b->d_slot_lds, b->slot_lds.data(), b->cap * sizeof(int), hipMemcpyHostToDevice);
+    if (e) return bfail(HCN_EDEVICE, hipGetErrorString(e));
+    b->dirty = false;
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    return HCN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nslots,
+                     int max_systems, const hcn_track_params *prm, int relax_k) {
+    if (!out || !prm) return bfail(HCN_EINVAL, "hcn_batch_create: NULL argument");
+    *out = nullptr;
+    if ((P != 2 && P != 4) || capacity < 1 || max_n < 1 || max_n > 1024 || max_nslots < 1 ||
+        max_systems < 1 || relax_k < 1)
+        return bfail(HCN_EINVAL, "hcn_batch_create: bad sizes (P 2/4, capacity >= 1, 1 <= max_n <= 1024)");
+    if (prm->max_iter < 1 || prm->max_iter > 100 || prm->max_steps < 0 || prm->end_iters < 0 ||
+        !(prm->max_dt > 0.0) || prm->max_dt > 1.0 || !(prm->min_dt > 0.0))
+        return bfail(HCN_EINVAL, "hcn_batch_create: bad tracking parameters");
+    auto *b = new hcn_batch_s;
+    b->P = P;
+    b->cap = capacity;
+    b->max_n = max_n;
+    b->max_nslots = max_nslots;
+    b->max_sys = max_systems;
+    const long W = 2 * P;
+    const long cap = capacity;
+    const long xs = max_n * W;
+    const long scs = std::max<long>((long)max_nslots * W, xs);  // scratch also holds dx
+    const long Js = (long)(max_n + 1) * max_n * W;
+    const long Rs = Js;
+    const long invs = (long)max_n * P;
+    const long nps = ((long)max_n * max_n + max_n + 255) / 256;
+    b->mon_cap = cap * ((max_nslots + 255) / 256 + 1);
+    b->sum_cap = cap * nps;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += al(bytes);
+        return o;
+    };
+    const size_t o_x = take(cap * xs * 8), o_xa = take(cap * xs * 8), o_xp = take(cap * xs * 8),
+                 o_xo = take(cap * xs * 8), o_sc = take(cap * scs * 8), o_J = take(cap * Js * 8),
+                 o_R = take(cap * Rs * 8), o_inv = take(cap * invs * 8), o_np = take(cap * nps * 8),
+                 o_t = take(cap * 8), o_g = take(cap * W * 8), o_st = take(cap * sizeof(PathState)),
+                 o_res = take(cap * sizeof(hcn_path_result)), o_sys = take(max_systems * sizeof(SysView)),
+                 o_ss = take(cap * 4), o_sl = take(cap * 4), o_mon = take(b->mon_cap * sizeof(int2)),
+                 o_sum = take(b->sum_cap * sizeof(int2)), o_slots = take(cap * 4), o_done = take(cap * 4),
+                 o_run = take(4);
+    b->bytes = off;
+    if (hipMalloc(&b->dmem, off) != hipSuccess) {
+        delete b;
+        return bfail(HCN_ENOMEM, "hcn_batch_create: device allocation failed");
+    }
+    char *base = (char *)b->dmem;
+    BatchDev &d = b->d;
+    d.P = P;
+    d.max_n = max_n;
+    d.relax_k = relax_k;
+    d.x = (double *)(base + o_x);
+    d.x_acc = (double *)(base + o_xa);
+    d.x_prev = (double *)(base + o_xp);
+    d.x_out = (double *)(base + o_xo);
+    d.sc = (double *)(base + o_sc);
+    d.J = (double *)(base + o_J);
+    d.R = (double *)(base + o_R);
+    d.inv = (double *)(base + o_inv);
+    d.np = (double *)(base + o_np);
+    d.t = (double *)(base + o_t);
+    d.gamma = (double *)(base + o_g);
+    d.st = (PathState *)(base + o_st);
+    d.res = (hcn_path_result *)(base + o_res);
+    d.xs = xs;
+    d.scs = scs;
+    d.Js = Js;
+    d.Rs = Rs;
+    d.invs = invs;
+    d.nps = nps;
+    d.max_nparts = (int)nps;
+    b->d_sys = (SysView *)(base + o_sys);
+    b->d_slot_sys = (int *)(base + o_ss);
+    b->d_slot_lds = (int *)(base + o_sl);
+    b->d_mon = (int2 *)(base + o_mon);
+    b->d_sum = (int2 *)(base + o_sum);
+    b->d_slots = (int *)(base + o_slots);
+    b->d_done = (int32_t *)(base + o_done);
+    b->d_running = (int32_t *)(base + o_run);
+    d.sys = b->d_sys;
+    d.slot_sys = b->d_slot_sys;
+    d.slot_lds = b->d_slot_lds;
+    TrackArgs &ta = d.prm;
+    ta.P = P;
+    ta.max_iter = prm->max_iter;
+    ta.max_steps = prm->max_steps;
+    ta.end_iters = prm->end_iters;
+    ta.predictor_order = prm->predictor_order;
+    ta.tol_res = prm->tol_res;
+    ta.tol_dx = prm->tol_dx;
+    ta.max_eq_val = prm->max_eq_val;
+    ta.max_dt = prm->max_dt;
+    ta.min_dt = prm->min_dt;
+    ta.end_tol = prm->end_tol;
+    b->slot_sys.assign(capacity, -1);
+    b->slot_lds.assign(capacity, 0);
+    if (hipHostMalloc((void **)&b->h_running, sizeof(int32_t)) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_done, sizeof(int32_t) * capacity) != hipSuccess) {
+        (void)hipFree(b->dmem);
+        delete b;
+        return bfail(HCN_ENOMEM, "hcn_batch_create: pinned allocation failed");
+    }
+    if (P == 2)
+        set_lds_attributes<dd>();
+    else
+        set_lds_attributes<qd>();
+    *out = b;
+    return HCN_OK;
+}
+
+int hcn_batch_destroy(hcn_batch b) {
+    if (!b) return HCN_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    (void)hipHostFree(b->h_running);
+    (void)hipHostFree(b->h_done);
+    (void)hipFree(b->dmem);
+    delete b;
+    return HCN_OK;
+}
+
+size_t hcn_batch_device_bytes(hcn_batch b) { return b ? b->bytes : 0; }
+
+int hcn_batch_add(hcn_batch b, int slot, hcn_sys sys, const double *gamma, const double *x0,
+                  void *stream) {
+    if (!b || !sys || !gamma || !x0) return bfail(HCN_EINVAL, "hcn_batch_add: NULL argument");
+    if (slot < 0 || slot >= b->cap) return bfail(HCN_EINVAL, "hcn_batch_add: slot out of range");
+    if (b->slot_sys[slot] >= 0) return bfail(HCN_EINVAL, "hcn_batch_add: slot is occupied");
+    hcn_sys_info_t info;
+    hcn_sys_info(sys, &info);
+    if (info.P != b->P) return bfail(HCN_EINVAL, "hcn_batch_add: precision differs from the batch");
+    if (info.N != info.n) return bfail(HCN_EINVAL, "hcn_batch_add: tracking needs N == n");
+    if (info.n > b->max_n || info.nslots > b->max_nslots)
+        return bfail(HCN_EINVAL, "hcn_batch_add: system larger than the batch was sized for");
+    int idx = -1;
+    for (size_t q = 0; q < b->systems.size(); ++q)
+        if (b->systems[q] == sys) idx = (int)q;
+    if (idx < 0) {
+        if ((int)b->systems.size() >= b->max_sys)
+            return bfail(HCN_EINVAL, "hcn_batch_add: too many distinct systems");
+        idx = (int)b->systems.size();
+        b->systems.push_back(sys);
+        const SysView v = sys_view(sys);
+        b->views.push_back(v);
+        if (hipMemcpy(b->d_sys + idx, &v, sizeof(SysView), hipMemcpyHostToDevice) != hipSuccess)
+            return bfail(HCN_EDEVICE, "hcn_batch_add: registry upload failed");
+        b->kb = std::max(b->kb, kbucket_b(v.max_k));
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const long W = 2 * b->P;
+    if (hipMemcpyAsync(b->d.gamma + (size_t)slot * W, gamma, sizeof(double) * W,
+                       hipMemcpyHostToDevice, s) != hipSuccess)
+        return bfail(HCN_EDEVICE, "hcn_batch_add: gamma upload failed");
+    b->slot_sys[slot] = idx;
+    // the slot table on the device must know the slot before its init runs
+    if (hipMemcpyAsync(b->d_slot_sys + slot, &b->slot_sys[slot], sizeof(int), hipMemcpyHostToDevice,
+                       s) != hipSuccess)
+        return bfail(HCN_EDEVICE, "hcn_batch_add: slot upload failed");
+    if (b->P == 2)
+        hipLaunchKernelGGL(k_b_init<dd>, dim3(1), dim3(64), 0, s, b->d, slot, x0);
+    else
+        hipLaunchKernelGGL(k_b_init<qd>, dim3(1), dim3(64), 0, s, b->d, slot, x0);
+    b->dirty = true;
+    return hipGetLastError() == hipSuccess ? HCN_OK : bfail(HCN_EDEVICE, "hcn_batch_add: launch failed");
+}
+
+int hcn_batch_release(hcn_batch b, int slot) {
+    if (!b || slot < 0 || slot >= b->cap) return bfail(HCN_EINVAL, "hcn_batch_release: bad slot");
+    b->slot_sys[slot] = -1;
+    b->dirty = true;
+    return HCN_OK;
+}
+
+int hcn_batch_step(hcn_batch b, int steps, void *stream) {
+    if (!b || steps < 0) return bfail(HCN_EINVAL, "hcn_batch_step: bad argument");
+    hipStream_t s = (hipStream_t)stream;
+    if (b->dirty) {
+        // the slot table may only change between steps: wait for pending work
+        if (hipStreamSynchronize(s) != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_step: sync");
+        const int rc = rebuild(b);
+        if (rc) return rc;
+    }
+    if (b->n_slots == 0 || steps == 0) return HCN_OK;
+    if (!b->exec || b->exec_stream != s) {
+        if (b->exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->exec = nullptr;
+        }
+        hipGraph_t g = nullptr;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return bfail(HCN_EDEVICE, "hcn_batch_step: capture begin failed");
+        const int e = b->P == 2 ? enqueue_step<dd>(b, s) : enqueue_step<qd>(b, s);
+        const hipError_t ec = hipStreamEndCapture(s, &g);
+        if (e || ec != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_step: capture failed");
+        const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_step: instantiate failed");
+        b->exec_stream = s;
+    }
+    ProfScope prof("batch_step", s);
+    for (int q = 0; q < steps; ++q)
+        if (hipGraphLaunch(b->exec, s) != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_step: graph launch failed");
+    return HCN_OK;
+}
+
+int hcn_batch_poll(hcn_batch b, int32_t *done, void *stream) {
+    if (!b) return bfail(HCN_EINVAL, "hcn_batch_poll: NULL batch");
+    hipStream_t s = (hipStream_t)stream;
+    if (b->dirty) {
+        if (hipStreamSynchronize(s) != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_poll: sync");
+        const int rc = rebuild(b);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_b_flags, dim3(1), dim3(256), 0, s, b->d, b->cap, b->d_done, b->d_running);
+    hipError_t e = hipMemcpyAsync(b->h_running, b->d_running, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (!e && done) e = hipMemcpyAsync(b->h_done, b->d_done, sizeof(int32_t) * b->cap, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    if (e) return bfail(HCN_EDEVICE, "hcn_batch_poll: copy failed");
+    if (done) std::memcpy(done, b->h_done, sizeof(int32_t) * b->cap);
+    return *b->h_running;
+}
+
+int hcn_batch_result(hcn_batch b, int slot, double *x_out, hcn_path_result *res, void *stream) {
+    if (!b || slot < 0 || slot >= b->cap || b->slot_sys[slot] < 0)
+        return bfail(HCN_EINVAL, "hcn_batch_result: bad slot");
+    hipStream_t s = (hipStream_t)stream;
+    const SysView &v = b->views[b->slot_sys[slot]];
+    hipError_t e = hipSuccess;
+    if (x_out)
+        e = hipMemcpyAsync(x_out, b->d.x_out + (size_t)slot * b->d.xs, sizeof(double) * v.n * 2 * b->P,
+                           hipMemcpyDeviceToDevice, s);
+    if (!e && res) {
+        e = hipMemcpyAsync(res, b->d.res + slot, sizeof(hcn_path_result), hipMemcpyDeviceToHost, s);
+        if (!e) e = hipStreamSynchronize(s);
+    }
+    return e ? bfail(HCN_EDEVICE, "hcn_batch_result: copy failed") : HCN_OK;
+}
+
+int hcn_batch_run(hcn_batch b, int chunk, void *stream) {
+    if (!b || chunk < 1) return bfail(HCN_EINVAL, "hcn_batch_run: bad argument");
+    const long bound = (long)b->d.prm.max_steps + 3 +
+                       (b->d.prm.end_iters + b->d.prm.max_iter - 1) / b->d.prm.max_iter + 2;
+    long done_steps = 0;
+    int running = hcn_batch_poll(b, nullptr, stream);
+    while (running > 0 && done_steps < bound + chunk) {
+        const int rc = hcn_batch_step(b, chunk, stream);
+        if (rc) return rc;
+        done_steps += chunk;
+        running = hcn_batch_poll(b, nullptr, stream);
+        if (running < 0) return running;
+    }
+    return running == 0 ? HCN_OK : bfail(HCN_EDEVICE, "hcn_batch_run: paths unfinished after the step bound");
+}
+
+}  // extern "C"

@@ -94,6 +94,8 @@ struct hcn_sys_s {
     std::vector<int32_t> deg;
 };
 
+SysView hcn::sys_view(hcn_sys s) { return s->v; }
+
 extern "C" {
 
 const char *hcn_last_error(void) { return g_err.c_str(); }

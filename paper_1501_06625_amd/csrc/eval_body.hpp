@@ -1,0 +1,224 @@
+// eval_body.hpp -- per-lane bodies of the evaluation kernels, shared by the
+// single-system kernels (eval.hip) and the slot-table kernels (batch.hip).
+//
+// mon_one: reverse mode on the product of the k distinct variables
+// y_0..y_{k-1} of one monomial (Section 3.2, Table 1):
+//   forward  F_0 = y_0, F_p = F_{p-1} y_p            (p = 1..k-2)
+//   value    S = F_{k-2} y_{k-1}
+//   backward dS/dy_{k-1} = F_{k-2}; B = y_{k-1};
+//            for p = k-2..1: dS/dy_p = F_{p-1} B, B = B y_p;  dS/dy_0 = B
+// i.e. 3k-5 complex products.  Exponents above one: m = c x^a is c' S with
+// the common factor c' = c prod x_l^(a_l - 1), and dm/dx_l = a_l c' dS/dy_l.
+// The value and the k partials go to consecutive slots of the monomial's
+// k-group (position-major, so a wavefront writes 64 consecutive slots).
+//
+// sum_one: one output, the sum of its slot list in input monomial order
+// (Section 3.3), with the homotopy of equation (1) for the total-degree
+// start system fused in.
+#pragma once
+
+#include "internal.hpp"
+#include "mp.hpp"
+
+namespace hcn {
+
+enum { MON_FREG = 0, MON_FSLOT = 1, MON_VALUES = 2 };
+
+template <class R>
+HCN_DEV cx<R> load_y(const SysView &s, const double *xb, int xP, int p, int m) {
+    const int v = s.pos[(size_t)p * s.nmon + m];
+    return cload_s<R>(xb + (size_t)v * 2 * xP, xP);
+}
+
+template <class R>
+HCN_DEV cx<R> cpow_small(const cx<R> &y, int e) {
+    // y^e for e >= 1 by repeated multiplication
+    cx<R> r = y;
+    for (int q = 1; q < e; ++q) r = cmul(r, y);
+    return r;
+}
+
+// MODE: MON_FREG keeps the forward products in registers (KB-1 of them);
+// MON_FSLOT parks them in the output slots of the partials they precede and
+// reads them back in the backward sweep; MON_VALUES forms values only.
+template <class R, int KB, int MODE>
+HCN_DEV void mon_one(const SysView &s, int m, const double *xb, int xP, double *out) {
+    constexpr int W = 2 * limbs<R>::P;
+    const int k = s.mon_k[m];
+    const int slot = s.mon_slot[m];
+    const int stride = s.mon_stride[m];
+    const cx<R> c = cload_s<R>(s.coef + (size_t)m * 2 * s.P, s.P);
+    if (k == 0) {
+        cstore(out + (size_t)slot * W, c);
+        return;
+    }
+    cx<R> F[MODE == MON_FREG ? (KB > 1 ? KB - 1 : 1) : 1];
+    cx<R> Flast = czero<R>(), ylast = czero<R>(), pc = czero<R>();
+    bool has_pc = false;
+#pragma unroll
+    for (int p = 0; p < KB; ++p) {
+        if (p < k) {
+            const cx<R> y = load_y<R>(s, xb, xP, p, m);
+            const int e = s.ex[(size_t)p * s.nmon + m];
+            if (e >= 2) {
+                const cx<R> pw = cpow_small(y, e - 1);
+                pc = has_pc ? cmul(pc, pw) : pw;
+                has_pc = true;
+            }
+            if (p <= k - 2) {
+                const cx<R> Fp = (p == 0) ? y : cmul(Flast, y);
+                if (MODE == MON_FREG) {
+                    F[MODE == MON_FREG ? p : 0] = Fp;
+                } else if (MODE == MON_FSLOT) {
+                    cstore(out + (size_t)(slot + (p + 2) * stride) * W, Fp);
+                }
+                Flast = Fp;
+            } else {
+                ylast = y;
+            }
+        }
+    }
+    const cx<R> cp = has_pc ? cmul(c, pc) : c;
+    if (k == 1) {
+        cstore(out + (size_t)slot * W, cmul(cp, ylast));
+        if (MODE != MON_VALUES) {
+            const int a0 = s.ex[m];
+            const cx<R> d = (a0 == 1) ? cp : cscale_d(cp, (double)a0);
+            cstore(out + (size_t)(slot + stride) * W, d);
+        }
+        return;
+    }
+    const cx<R> S = cmul(Flast, ylast);
+    cstore(out + (size_t)slot * W, cmul(cp, S));
+    if (MODE == MON_VALUES) return;
+    {
+        const int e = s.ex[(size_t)(k - 1) * s.nmon + m];
+        cx<R> d = cmul(cp, Flast);
+        if (e != 1) d = cscale_d(d, (double)e);
+        cstore(out + (size_t)(slot + k * stride) * W, d);
+    }
+    cx<R> Bk = ylast;
+#pragma unroll
+    for (int p = KB - 2; p >= 1; --p) {
+        if (p <= k - 2) {
+            cx<R> Fpm1;
+            if (MODE == MON_FREG) {
+                Fpm1 = F[MODE == MON_FREG ? p - 1 : 0];
+            } else {
+                Fpm1 = cload<R>(out + (size_t)(slot + (p + 1) * stride) * W);
+            }
+            const int e = s.ex[(size_t)p * s.nmon + m];
+            cx<R> d = cmul(cp, cmul(Fpm1, Bk));
+            if (e != 1) d = cscale_d(d, (double)e);
+            cstore(out + (size_t)(slot + (p + 1) * stride) * W, d);
+            Bk = cmul(Bk, load_y<R>(s, xb, xP, p, m));
+        }
+    }
+    {
+        const int e = s.ex[m];
+        cx<R> d = cmul(cp, Bk);
+        if (e != 1) d = cscale_d(d, (double)e);
+        cstore(out + (size_t)(slot + stride) * W, d);
+    }
+}
+
+template <class R>
+HCN_DEV cx<R> sum_list(const double *sc, const int32_t *list, int a, int b) {
+    constexpr int W = 2 * limbs<R>::P;
+    if (a >= b) return czero<R>();
+    cx<R> acc = cload<R>(sc + (size_t)list[a] * W);
+    for (int q = a + 1; q < b; ++q) acc = cadd(acc, cload<R>(sc + (size_t)list[q] * W));
+    return acc;
+}
+
+template <class R>
+HCN_DEV R r_from_two(double s, double e);
+template <>
+HCN_DEV double r_from_two<double>(double s, double e) { return s + e; }
+template <>
+HCN_DEV dd r_from_two<dd>(double s, double e) { return dd{s, e}; }
+template <>
+HCN_DEV qd r_from_two<qd>(double s, double e) { return qd{s, e, 0.0, 0.0}; }
+
+// where one path's sums go
+struct SumOut {
+    int jac;            // 0: values only (entries 0..N-1 are f)
+    double *J;          // column k at J + k*J_cstride, or NULL
+    long J_cstride;
+    double *f;          // or NULL
+    int f_neg, f_lead_only;
+};
+
+// output e of one path (e < n N: Jacobian entry (e / N, e % N); else f_{e - nN});
+// returns the leading-limb magnitude of an f entry (0 for Jacobian entries)
+template <class R>
+HCN_DEV double sum_one(const SysView &s, long e, const double *sc, const double *xb, int xP,
+                       int hom_on, int relax_k, double t, const double *gamma, int gP,
+                       const SumOut &o) {
+    constexpr int W = 2 * limbs<R>::P;
+    const long nJ = o.jac ? (long)s.n * s.N : 0;
+    if (e >= nJ + s.N) return 0.0;
+    const bool isJ = e < nJ;
+    const int k = isJ ? (int)(e / s.N) : -1;
+    const int i = isJ ? (int)(e % s.N) : (int)(e - nJ);
+    cx<R> acc = isJ ? sum_list<R>(sc, s.J_list, s.J_ptr[e], s.J_ptr[e + 1])
+                    : sum_list<R>(sc, s.f_list, s.f_ptr[i], s.f_ptr[i + 1]);
+    if (hom_on) {
+        // s_f = t^k, s_g = gamma (1-t)^k (1-t formed exactly)
+        const R tt = rmake<R>(t);
+        R sf = tt;
+        for (int q = 1; q < relax_k; ++q) sf = mul(sf, tt);
+        if (!isJ || k == i) {
+            double os, oe;
+            eft_sum(1.0, -t, os, oe);
+            const R omt = r_from_two<R>(os, oe);
+            R pw = omt;
+            for (int q = 1; q < relax_k; ++q) pw = mul(pw, omt);
+            const cx<R> gam = cload_s<R>(gamma, gP);
+            const cx<R> sg = cscale(pw, gam);
+            const cx<R> xi = cload_s<R>(xb + (size_t)i * 2 * xP, xP);
+            const int d = s.deg[i];
+            cx<R> xpm1 = cone<R>();
+            if (d >= 2) xpm1 = cpow_small(xi, d - 1);
+            if (isJ) {
+                const cx<R> dg = cscale_d(xpm1, (double)d);
+                acc = cadd(cmul(sg, dg), cscale(sf, acc));
+            } else {
+                const cx<R> xd = (d >= 2) ? cmul(xpm1, xi) : xi;
+                const cx<R> g = csub(xd, cone<R>());
+                acc = cadd(cmul(sg, g), cscale(sf, acc));
+            }
+        } else {
+            acc = cscale(sf, acc);
+        }
+    }
+    if (isJ) {
+        if (o.J) cstore(o.J + (size_t)k * o.J_cstride + (size_t)i * W, acc);
+        return 0.0;
+    }
+    const double mx = clead_abs(acc);
+    if (o.f_neg) acc = cneg(acc);
+    if (o.f) {
+        if (o.f_lead_only) {
+            double *p = o.f + (size_t)i * 2;
+            p[0] = lead(acc.re);
+            p[1] = lead(acc.im);
+        } else {
+            cstore(o.f + (size_t)i * W, acc);
+        }
+    }
+    return mx;
+}
+
+// maximum over a 256-lane workgroup (NaN propagates); every lane returns it
+HCN_DEV double block_max(double mx, double *red) {
+    for (int off = 32; off >= 1; off >>= 1) mx = nanmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    double r = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = nanmax(r, red[w]);
+    __syncthreads();
+    return r;
+}
+
+}  // namespace hcn

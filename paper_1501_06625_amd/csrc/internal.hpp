@@ -132,6 +132,15 @@ int launch_mgs(int RP, const MgsArgs &a, hipStream_t stream);
 // holds 2B+1 ints of workspace
 int launch_mgs_big(int P, const MgsArgs &a, int variant, int *ints_dev, hipStream_t stream);
 size_t mgs_res_lds(int N, int n, int P);
+// the device tables of a loaded system (capi.hip)
+SysView sys_view(hcn_sys s);
+
+// kernel-variant table (tune.hip)
+int tune_mgs_group(int P, int N);
+int tune_mgs_lds(int P, int N);
+size_t mgs_lds_limit();
+void tune_set(int P, int N, int group, int lds);
+
 // Fig. 2 tests before a solve, one lane per problem (norm parts of a.norm_part)
 int launch_fig2_pre(const MgsArgs &a, hipStream_t stream);
 // mixed precision: x (xP limbs) += dx (double), the update norm and the Fig. 2

@@ -280,14 +280,14 @@ __global__ __launch_bounds__(BT) void k_mgs_res(MgsArgs a, ResArgs r) {
 // ---------------------------------------------------------------------------
 __global__ void k_fig2_pre(MgsArgs a) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b < a.B) (void)fig2_decide(a, b);
+    if (b < a.B) (void)fig2_decide(problem_of(a, b));
 }
 
 template <class R>
 __global__ __launch_bounds__(BT) void k_mgs_finish(MgsArgs a, const int *sing) {
     const int b = blockIdx.x;
     if (!problem_live(a, b)) return;
-    mgs_epilogue<R>(a, b, sing[b] != 0);
+    mgs_epilogue<R>(problem_of(a, b), sing[b] != 0);
 }
 
 __global__ void k_zero_int(int *p, int count) {

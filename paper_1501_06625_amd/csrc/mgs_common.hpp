@@ -1,9 +1,18 @@
-// mgs_common.hpp -- the parts of the solve shared by every MGS variant: the
-// Fig. 2 tests taken before a solve, and the epilogue after the
-// factorisation (column-oriented back substitution dx_k = y_k / r_kk,
-// y_i -= r_ik dx_k for i < k; the Newton update x += dx with its norm and the
-// Fig. 2 tests that follow it).  The epilogue runs in one workgroup of
-// MGS_THREADS lanes per problem.
+// mgs_common.hpp -- modified Gram-Schmidt on the augmented matrix [A | b] in
+// one workgroup per problem (Section 1; Fig. 2, GPU_Modified_Gram_Schmidt),
+// the Fig. 2 tests around a solve, and the epilogue every MGS variant shares
+// (column-oriented back substitution dx_k = y_k / r_kk, y_i -= r_ik dx_k for
+// i < k; the Newton update x += dx with its norm and the Fig. 2 tests that
+// follow it).
+//
+// mgs_wg: right-looking.  For column k the first lane group forms
+// ||a_k||^2, one lane takes r_kk = sqrt, 1/r_kk, every lane scales its rows
+// of a_k, then each lane group owns trailing columns j > k (the right-hand
+// side last), forms r_kj = q_k^H a_j over its rows and a butterfly across
+// its GROUP lanes, and updates a_j -= r_kj q_k on its rows.  Butterflies add
+// the lower lane's value first, so every lane of a group holds bitwise the
+// same sum.  When [A | b] fits in LDS the workgroup copies it there first;
+// the arithmetic is the same either way.
 #pragma once
 
 #include "internal.hpp"
@@ -13,14 +22,57 @@ namespace hcn {
 
 constexpr int MGS_THREADS = 256;
 
+// one problem with every pointer resolved
+struct MgsProblem {
+    int N, n, mode, lds;
+    double *A;          // column j at A + j*A_cstride (j < n)
+    long A_cstride;
+    double *bcol;       // column n
+    double *R;          // [n+1][n][2P]
+    double *inv;        // [n][P]
+    double *dx;         // [n][2P]
+    int32_t *status;    // or NULL
+    double *x;          // Newton modes: [n][2P]
+    const double *norm_part;
+    int nparts;
+    double *norms;      // [2] or NULL
+    PathState *st;      // Fig. 2 modes
+};
+
+HCN_DEV MgsProblem problem_of(const MgsArgs &a, int b) {
+    MgsProblem p;
+    p.N = a.N;
+    p.n = a.n;
+    p.mode = a.mode;
+    p.lds = 0;
+    p.A = a.A + (size_t)b * a.A_pstride;
+    p.A_cstride = a.A_cstride;
+    p.bcol = a.bcol ? a.bcol + (size_t)b * a.b_pstride : p.A + (size_t)a.n * a.A_cstride;
+    p.R = a.R + (size_t)b * a.R_pstride;
+    p.inv = a.inv + (size_t)b * a.inv_pstride;
+    p.dx = a.dx + (size_t)b * a.dx_pstride;
+    p.status = a.status ? a.status + b : nullptr;
+    p.x = a.x ? a.x + (size_t)b * a.x_pstride : nullptr;
+    p.norm_part = a.norm_part ? a.norm_part + (size_t)b * a.nparts : nullptr;
+    p.nparts = a.nparts;
+    p.norms = a.norms ? a.norms + 2 * (size_t)b : nullptr;
+    p.st = a.st ? a.st + b : nullptr;
+    return p;
+}
+
+HCN_DEV double residual_norm(const MgsProblem &p) {
+    double res = 0.0;
+    for (int q = 0; q < p.nparts; ++q) res = nanmax(res, p.norm_part[q]);
+    return res;
+}
+
 // Fig. 2 before the solve: fail if the residual grew beyond the previous one
 // (initially max_eq_val), succeed if it is below the tolerance, stop on NaN.
 // Called by one lane; returns 1 when this problem needs no solve.
-HCN_DEV int fig2_decide(const MgsArgs &a, int b) {
-    PathState &st = a.st[b];
+HCN_DEV int fig2_decide(const MgsProblem &p) {
+    PathState &st = *p.st;
     if (!st.c_active) return 1;
-    double res = 0.0;
-    for (int q = 0; q < a.nparts; ++q) res = nanmax(res, a.norm_part[(size_t)b * a.nparts + q]);
+    const double res = residual_norm(p);
     st.res = res;
     st.c_iter += 1;
     int decided = 0;
@@ -38,60 +90,70 @@ HCN_DEV int fig2_decide(const MgsArgs &a, int b) {
     return decided;
 }
 
+// Fig. 2 after the update
+HCN_DEV void fig2_after_update(PathState &st, double dxn) {
+    st.dxn = dxn;
+    if (dxn != dxn) {
+        st.c_status = HCN_NAN;
+        st.c_active = 0;
+    } else if (dxn < st.tol_dx) {
+        st.c_status = HCN_OK;
+        st.c_active = 0;
+    } else {
+        st.last = st.res;
+        if (st.c_iter >= st.c_maxit) {
+            st.c_status = HCN_NOT_CONVERGED;
+            st.c_active = 0;
+        }
+    }
+}
+
 template <class R>
-HCN_DEV void mgs_epilogue(const MgsArgs &a, int b, bool singular) {
+HCN_DEV void mgs_epilogue(const MgsProblem &p, bool singular) {
     constexpr int P = limbs<R>::P;
     constexpr int W = 2 * P;
     const int tid = threadIdx.x;
-    const int n = a.n;
-    double *Rb = a.R + (size_t)b * a.R_pstride;
-    double *invb = a.inv + (size_t)b * a.inv_pstride;
-    double *dxb = a.dx + (size_t)b * a.dx_pstride;
+    const int n = p.n;
     if (singular) {
         if (tid == 0) {
-            if (a.status) a.status[b] = HCN_ESINGULAR;
-            if (a.mode == MGS_NEWTON_FIG2 || a.mode == MGS_MIXED_SOLVE) {
-                a.st[b].c_status = HCN_ESINGULAR;
-                a.st[b].c_active = 0;
+            if (p.status) *p.status = HCN_ESINGULAR;
+            if (p.mode == MGS_NEWTON_FIG2 || p.mode == MGS_MIXED_SOLVE) {
+                p.st->c_status = HCN_ESINGULAR;
+                p.st->c_active = 0;
             }
-            if (a.mode == MGS_NEWTON_STEP && a.norms) {
-                double res = 0.0;
-                for (int q = 0; q < a.nparts; ++q) res = nanmax(res, a.norm_part[(size_t)b * a.nparts + q]);
-                a.norms[2 * b] = res;
-                a.norms[2 * b + 1] = __builtin_nan("");
+            if (p.mode == MGS_NEWTON_STEP && p.norms) {
+                p.norms[0] = residual_norm(p);
+                p.norms[1] = __builtin_nan("");
             }
         }
         return;
     }
-
-    // ---- back substitution, in place in dx (starts as y = column n of R)
+    // back substitution, in place in dx (starts as y = column n of R)
     for (int i = tid; i < n; i += MGS_THREADS)
-        cstore(dxb + (size_t)i * W, cload<R>(Rb + ((size_t)n * n + i) * W));
+        cstore(p.dx + (size_t)i * W, cload<R>(p.R + ((size_t)n * n + i) * W));
     __syncthreads();
     for (int k = n - 1; k >= 0; --k) {
         if (tid == 0) {
             R iv;
-            rload(invb + (size_t)k * P, iv);
-            cstore(dxb + (size_t)k * W, cscale(iv, cload<R>(dxb + (size_t)k * W)));
+            rload(p.inv + (size_t)k * P, iv);
+            cstore(p.dx + (size_t)k * W, cscale(iv, cload<R>(p.dx + (size_t)k * W)));
         }
         __syncthreads();
-        const cx<R> xk = cload<R>(dxb + (size_t)k * W);
+        const cx<R> xk = cload<R>(p.dx + (size_t)k * W);
         for (int i = tid; i < k; i += MGS_THREADS) {
-            double *p = dxb + (size_t)i * W;
-            cstore(p, csub(cload<R>(p), cmul(cload<R>(Rb + ((size_t)k * n + i) * W), xk)));
+            double *q = p.dx + (size_t)i * W;
+            cstore(q, csub(cload<R>(q), cmul(cload<R>(p.R + ((size_t)k * n + i) * W), xk)));
         }
         __syncthreads();
     }
-
-    if (a.mode == MGS_SOLVE || a.mode == MGS_MIXED_SOLVE) {
-        if (tid == 0 && a.status) a.status[b] = HCN_OK;
+    if (p.mode == MGS_SOLVE || p.mode == MGS_MIXED_SOLVE) {
+        if (tid == 0 && p.status) *p.status = HCN_OK;
         return;
     }
-
-    // ---- Newton: update norm, NaN check, x += dx
+    // Newton: update norm, NaN check, x += dx
     __shared__ double s_red[MGS_THREADS / 64];
     double m = 0.0;
-    for (int i = tid; i < n; i += MGS_THREADS) m = nanmax(m, clead_abs(cload<R>(dxb + (size_t)i * W)));
+    for (int i = tid; i < n; i += MGS_THREADS) m = nanmax(m, clead_abs(cload<R>(p.dx + (size_t)i * W)));
     for (int off = 32; off >= 1; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
     if ((tid & 63) == 0) s_red[tid >> 6] = m;
     __syncthreads();
@@ -99,39 +161,153 @@ HCN_DEV void mgs_epilogue(const MgsArgs &a, int b, bool singular) {
     for (int w = 1; w < MGS_THREADS / 64; ++w) dxn = nanmax(dxn, s_red[w]);
     const bool isnan_dx = dxn != dxn;
     if (!isnan_dx) {
-        double *xb = a.x + (size_t)b * a.x_pstride;
         for (int i = tid; i < n; i += MGS_THREADS) {
-            double *p = xb + (size_t)i * W;
-            cstore(p, cadd(cload<R>(p), cload<R>(dxb + (size_t)i * W)));
+            double *q = p.x + (size_t)i * W;
+            cstore(q, cadd(cload<R>(q), cload<R>(p.dx + (size_t)i * W)));
         }
     }
     if (tid == 0) {
-        if (a.mode == MGS_NEWTON_STEP) {
-            double res = 0.0;
-            for (int q = 0; q < a.nparts; ++q) res = nanmax(res, a.norm_part[(size_t)b * a.nparts + q]);
-            if (a.norms) {
-                a.norms[2 * b] = res;
-                a.norms[2 * b + 1] = dxn;
+        if (p.mode == MGS_NEWTON_STEP) {
+            if (p.norms) {
+                p.norms[0] = residual_norm(p);
+                p.norms[1] = dxn;
             }
-            if (a.status) a.status[b] = isnan_dx ? HCN_NAN : HCN_OK;
+            if (p.status) *p.status = isnan_dx ? HCN_NAN : HCN_OK;
         } else {
-            PathState &st = a.st[b];
-            st.dxn = dxn;
-            if (isnan_dx) {
-                st.c_status = HCN_NAN;
-                st.c_active = 0;
-            } else if (dxn < st.tol_dx) {
-                st.c_status = HCN_OK;
-                st.c_active = 0;
-            } else {
-                st.last = st.res;
-                if (st.c_iter >= st.c_maxit) {
-                    st.c_status = HCN_NOT_CONVERGED;
-                    st.c_active = 0;
+            fig2_after_update(*p.st, dxn);
+        }
+    }
+}
+
+HCN_DEV double gshfl(double v, int m) { return __shfl_xor(v, m); }
+HCN_DEV dd gshfl(const dd &v, int m) { return dd{gshfl(v.hi, m), gshfl(v.lo, m)}; }
+HCN_DEV qd gshfl(const qd &v, int m) {
+    return qd{gshfl(v.c0, m), gshfl(v.c1, m), gshfl(v.c2, m), gshfl(v.c3, m)};
+}
+
+// sum over the GRP consecutive lanes of a group, lower lane first
+template <class R, int GRP>
+HCN_DEV R group_sum(R v, int lane) {
+#pragma unroll
+    for (int m = 1; m < GRP; m <<= 1) {
+        const R o = gshfl(v, m);
+        v = (lane & m) ? add(o, v) : add(v, o);
+    }
+    return v;
+}
+
+template <class R, int GRP>
+HCN_DEV cx<R> group_csum(cx<R> v, int lane) {
+#pragma unroll
+    for (int m = 1; m < GRP; m <<= 1) {
+        const cx<R> o{gshfl(v.re, m), gshfl(v.im, m)};
+        v = (lane & m) ? cadd(o, v) : cadd(v, o);
+    }
+    return v;
+}
+
+// bytes of LDS that hold [A | b] of one problem
+HCN_DEV __host__ inline size_t mgs_lds_bytes(int N, int n, int P) {
+    return (size_t)(n + 1) * N * 2 * P * sizeof(double);
+}
+
+template <class R, int GRP>
+HCN_DEV void mgs_wg(const MgsProblem &p) {
+    constexpr int P = limbs<R>::P;
+    constexpr int W = 2 * P;
+    constexpr int NGRP = MGS_THREADS / GRP;
+    extern __shared__ double lds_cols[];
+    __shared__ int s_flag;
+    __shared__ double s_inv[4];
+    const int tid = threadIdx.x;
+    const int g = tid / GRP;
+    const int lane = tid % GRP;
+    const int N = p.N, n = p.n;
+
+    // Fig. 2 tests before the solve (residual norm against the previous one)
+    if (p.mode == MGS_NEWTON_FIG2 || p.mode == MGS_MIXED_SOLVE) {
+        if (tid == 0) s_flag = p.mode == MGS_NEWTON_FIG2 ? fig2_decide(p) : !p.st->c_active;
+        __syncthreads();
+        if (s_flag) return;
+    }
+    const size_t cst = (size_t)N * W;
+    if (p.lds) {
+        for (size_t q = tid; q < (size_t)(n + 1) * cst; q += MGS_THREADS) {
+            const int j = (int)(q / cst);
+            const size_t off = q - (size_t)j * cst;
+            const double *src = j < n ? p.A + (size_t)j * p.A_cstride : p.bcol;
+            lds_cols[q] = src[off];
+        }
+    }
+    auto col = [&](int j) -> double * {
+        if (p.lds) return lds_cols + (size_t)j * cst;
+        return j < n ? p.A + (size_t)j * p.A_cstride : p.bcol;
+    };
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+
+    for (int k = 0; k < n; ++k) {
+        double *ak = col(k);
+        if (g == 0) {
+            R s = rmake<R>(0.0);
+            bool first = true;
+            for (int i = lane; i < N; i += GRP) {
+                const R v = cnorm2(cload<R>(ak + (size_t)i * W));
+                s = first ? v : add(s, v);
+                first = false;
+            }
+            s = group_sum<R, GRP>(s, lane);
+            if (lane == 0) {
+                const R rkk = sqrt(s);
+                const bool bad = !(lead(rkk) > 0.0) || !rfinite(rkk);
+                if (bad) {
+                    s_flag = 1;
+                } else {
+                    const R iv = div(rmake<R>(1.0), rkk);
+                    rstore(p.inv + (size_t)k * P, iv);
+                    rstore(s_inv, iv);
+                    const cx<R> rc{rkk, rmake<R>(0.0)};
+                    cstore(p.R + ((size_t)k * n + k) * W, rc);
                 }
             }
         }
+        __syncthreads();
+        if (s_flag) break;
+        R iv;
+        rload(s_inv, iv);
+        for (int i = tid; i < N; i += MGS_THREADS) {
+            double *q = ak + (size_t)i * W;
+            cstore(q, cscale(iv, cload<R>(q)));
+        }
+        __syncthreads();
+        for (int j = k + 1 + g; j <= n; j += NGRP) {
+            double *aj = col(j);
+            cx<R> r = czero<R>();
+            bool first = true;
+            for (int i = lane; i < N; i += GRP) {
+                const cx<R> v = cmul_conj(cload<R>(ak + (size_t)i * W), cload<R>(aj + (size_t)i * W));
+                r = first ? v : cadd(r, v);
+                first = false;
+            }
+            r = group_csum<R, GRP>(r, lane);
+            if (lane == 0) cstore(p.R + ((size_t)j * n + k) * W, r);
+            for (int i = lane; i < N; i += GRP) {
+                double *q = aj + (size_t)i * W;
+                cstore(q, csub(cload<R>(q), cmul(r, cload<R>(ak + (size_t)i * W))));
+            }
+        }
+        __syncthreads();
     }
+    // a plain solve returns Q and the projected right-hand side in place
+    if (p.lds && p.mode == MGS_SOLVE && !s_flag) {
+        for (size_t q = tid; q < (size_t)(n + 1) * cst; q += MGS_THREADS) {
+            const int j = (int)(q / cst);
+            const size_t off = q - (size_t)j * cst;
+            double *dst = j < n ? p.A + (size_t)j * p.A_cstride : p.bcol;
+            dst[off] = lds_cols[q];
+        }
+    }
+    mgs_epilogue<R>(p, s_flag != 0);
 }
 
 }  // namespace hcn

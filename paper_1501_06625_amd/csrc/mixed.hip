@@ -38,22 +38,7 @@ __global__ __launch_bounds__(MGS_THREADS) void k_mixed_update(MgsArgs a) {
         }
     }
     __syncthreads();
-    if (tid == 0) {
-        st.dxn = dxn;
-        if (isnan_dx) {
-            st.c_status = HCN_NAN;
-            st.c_active = 0;
-        } else if (dxn < st.tol_dx) {
-            st.c_status = HCN_OK;
-            st.c_active = 0;
-        } else {
-            st.last = st.res;
-            if (st.c_iter >= st.c_maxit) {
-                st.c_status = HCN_NOT_CONVERGED;
-                st.c_active = 0;
-            }
-        }
-    }
+    if (tid == 0) fig2_after_update(st, dxn);
 }
 
 int launch_mixed_update(int xP, const MgsArgs &a, hipStream_t s) {

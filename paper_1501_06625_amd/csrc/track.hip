@@ -13,6 +13,7 @@
 // many steps as needed.
 #include "internal.hpp"
 #include "mp.hpp"
+#include "track_body.hpp"
 
 namespace hcn {
 
@@ -58,188 +59,33 @@ int launch_newton_finish(int B, const PathState *st, double *norms, int32_t *sta
     return (int)hipGetLastError();
 }
 
+HCN_DEV TrackPath path_of(const TrackArgs &a, int b) {
+    const size_t off = (size_t)b * a.n * 2 * a.P;
+    TrackPath p;
+    p.n = a.n;
+    p.st = a.st + b;
+    p.x = a.x + off;
+    p.x_acc = a.x_acc + off;
+    p.x_prev = a.x_prev + off;
+    p.x_out = a.x_out + off;
+    p.t = a.t + b;
+    p.res = a.res + b;
+    return p;
+}
+
 template <class R>
 __global__ void k_track_init(TrackArgs a, const double *x0) {
-    constexpr int W = 2 * limbs<R>::P;
-    const int b = blockIdx.x;
-    const size_t off = (size_t)b * a.n * W;
-    for (int q = threadIdx.x; q < a.n * W; q += blockDim.x) {
-        a.x_acc[off + q] = x0[off + q];
-        a.x[off + q] = x0[off + q];
-    }
-    if (threadIdx.x == 0) {
-        PathState s = {};
-        s.t_acc = 0.0;
-        s.dt = a.max_dt;
-        s.phase = PHASE_TRACK;
-        s.status = HCN_OK;
-        s.c_status = C_RUNNING;
-        a.st[b] = s;
-    }
+    track_init_one<R>(a, path_of(a, blockIdx.x), x0 + (size_t)blockIdx.x * a.n * 2 * a.P);
 }
 
 template <class R>
 __global__ void k_track_begin(TrackArgs a) {
-    constexpr int W = 2 * limbs<R>::P;
-    const int b = blockIdx.x;
-    __shared__ int s_mode;  // 0 idle, 1 predict, 2 copy x_acc (refine start)
-    __shared__ double s_t;
-    PathState &st = a.st[b];
-    if (threadIdx.x == 0) {
-        int mode = 0;
-        if (st.phase == PHASE_TRACK) {
-            if (st.steps > a.max_steps) {
-                st.status = HCN_MAX_STEPS;
-                st.phase = PHASE_DONE;
-                st.c_active = 0;
-            } else {
-                double t = st.t_acc + st.dt;
-                if (t > 1.0) t = 1.0;
-                st.t = t;
-                a.t[b] = t;
-                st.last = a.max_eq_val;
-                st.tol_res = a.tol_res;
-                st.tol_dx = a.tol_dx;
-                st.c_maxit = a.max_iter;
-                st.c_iter = 0;
-                st.res = 0.0;
-                st.dxn = 0.0;
-                st.c_active = a.max_iter > 0 ? 1 : 0;
-                st.c_status = a.max_iter > 0 ? C_RUNNING : HCN_NOT_CONVERGED;
-                s_t = t;
-                mode = 1;
-            }
-        } else if (st.phase == PHASE_REFINE && !st.refine_started) {
-            st.refine_started = 1;
-            st.t = 1.0;
-            a.t[b] = 1.0;
-            st.last = a.max_eq_val;
-            st.tol_res = a.end_tol;
-            st.tol_dx = a.end_tol;
-            st.c_maxit = a.end_iters;
-            st.c_iter = 0;
-            st.res = 0.0;
-            st.dxn = 0.0;
-            st.c_active = 1;
-            st.c_status = C_RUNNING;
-            mode = 2;
-        }
-        s_mode = mode;
-    }
-    __syncthreads();
-    const int mode = s_mode;
-    if (mode == 0) return;
-    const size_t off = (size_t)b * a.n * W;
-    if (mode == 2 || !st.have_prev || a.predictor_order < 1) {
-        for (int q = threadIdx.x; q < a.n * W; q += blockDim.x) a.x[off + q] = a.x_acc[off + q];
-        return;
-    }
-    // secant: x = x1 + r (x1 - x0), r = (t - t1) / (t1 - t0)
-    const double t = s_t;
-    const R num = rmake<R>(t - st.t_acc);
-    const R den = rmake<R>(st.t_acc - st.t_prev);
-    const R ratio = div(num, den);
-    for (int i = threadIdx.x; i < a.n; i += blockDim.x) {
-        const cx<R> x1 = cload<R>(a.x_acc + off + (size_t)i * W);
-        const cx<R> xp = cload<R>(a.x_prev + off + (size_t)i * W);
-        const cx<R> d = csub(x1, xp);
-        cstore(a.x + off + (size_t)i * W, cadd(x1, cscale(ratio, d)));
-    }
-}
-
-__device__ void write_result(const TrackArgs &a, int b, const PathState &st) {
-    hcn_path_result r;
-    r.status = st.status;
-    r.steps = st.steps;
-    r.newton_iters = st.newton_iters;
-    r.end_iters = st.end_iters;
-    r.end_status = st.end_status;
-    r.accepted = st.accepted;
-    r.t = st.t_acc;
-    r.res_norm = st.res;
-    r.dx_norm = st.dxn;
-    a.res[b] = r;
+    track_begin_one<R>(a, path_of(a, blockIdx.x));
 }
 
 template <class R>
 __global__ void k_track_end(TrackArgs a) {
-    constexpr int W = 2 * limbs<R>::P;
-    const int b = blockIdx.x;
-    __shared__ int s_copy;  // 0 none, 1 accept (x_prev <- x_acc, x_acc <- x),
-                            // 2 out <- x, 3 out <- x_acc
-    PathState &st = a.st[b];
-    if (threadIdx.x == 0) {
-        int copy = 0;
-        if (st.phase == PHASE_TRACK) {
-            const int cs = st.c_status;
-            st.newton_iters += st.c_iter;
-            if (cs == HCN_OK) {
-                st.t_prev = st.t_acc;
-                st.have_prev = 1;
-                st.t_acc = st.t;
-                st.accepted += 1;
-                st.nsucc += 1;
-                if (st.nsucc > 2) {
-                    double dt = 2.0 * st.dt;
-                    st.dt = dt > a.max_dt ? a.max_dt : dt;
-                }
-                st.steps += 1;
-                copy = 1;
-                if (st.t_acc >= 1.0) {
-                    if (a.end_iters > 0) {
-                        st.phase = PHASE_REFINE;
-                    } else {
-                        st.phase = PHASE_DONE;
-                        copy = 4;  // accept, then out <- x_acc
-                    }
-                }
-            } else if (cs == HCN_NAN) {
-                st.status = HCN_NAN;
-                st.phase = PHASE_DONE;
-                st.steps += 1;
-                copy = 3;
-            } else {
-                st.nsucc = 0;
-                st.dt = 0.5 * st.dt;
-                st.steps += 1;
-                if (st.dt < a.min_dt) {
-                    st.status = HCN_STEP_TOO_SMALL;
-                    st.phase = PHASE_DONE;
-                    copy = 3;
-                }
-            }
-            if (st.phase == PHASE_DONE) st.c_active = 0;
-        } else if (st.phase == PHASE_REFINE && st.refine_started && !st.c_active) {
-            st.end_iters = st.c_iter;
-            st.end_status = st.c_status == C_RUNNING ? HCN_NOT_CONVERGED : st.c_status;
-            st.phase = PHASE_DONE;
-            st.status = HCN_OK;
-            copy = 2;
-        }
-        if (st.phase == PHASE_DONE && !st.finalized) {
-            // paths stopped by the step limit in k_track_begin end here
-            if (copy == 0) copy = 3;
-            write_result(a, b, st);
-            st.finalized = 1;
-        }
-        s_copy = copy;
-    }
-    __syncthreads();
-    const int copy = s_copy;
-    if (copy == 0) return;
-    const size_t off = (size_t)b * a.n * W;
-    for (int q = threadIdx.x; q < a.n * W; q += blockDim.x) {
-        if (copy == 1 || copy == 4) {
-            const double xa = a.x_acc[off + q];
-            a.x_prev[off + q] = xa;
-            a.x_acc[off + q] = a.x[off + q];
-            if (copy == 4) a.x_out[off + q] = a.x[off + q];
-        } else if (copy == 2) {
-            a.x_out[off + q] = a.x[off + q];
-        } else {
-            a.x_out[off + q] = a.x_acc[off + q];
-        }
-    }
+    track_end_one<R>(a, path_of(a, blockIdx.x));
 }
 
 __global__ void k_track_count(TrackArgs a) {

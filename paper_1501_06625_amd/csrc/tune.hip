@@ -1,0 +1,96 @@
+// tune.hip -- kernel-variant table and the autotuner.
+//
+// Choices: the lane-group width of the one-workgroup MGS (8, 16 or 32 lanes
+// per column) and whether [A | b] is staged in LDS, per precision and row
+// count bucket.  hcn_autotune times a Newton step of a given system for every
+// choice (HIP events on the caller's stream) and keeps the fastest; the
+// table can be saved to and loaded from a text file (one line per entry:
+// "P Nbucket group lds").  A choice depends only on (P, N), never on what
+// else is in a batch, so a path gives the same bits alone and in a mix.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "internal.hpp"
+
+namespace hcn {
+namespace {
+struct Choice {
+    int group = 16;
+    int lds = 1;
+};
+std::mutex g_mu;
+std::map<std::pair<int, int>, Choice> g_table;
+
+int nbucket(int N) {
+    int b = 8;
+    while (b < N && b < 4096) b <<= 1;
+    return b;
+}
+
+Choice lookup(int P, int N) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_table.find({P, nbucket(N)});
+    return it == g_table.end() ? Choice{} : it->second;
+}
+}  // namespace
+
+int tune_mgs_group(int P, int N) { return lookup(P, N).group; }
+
+int tune_mgs_lds(int P, int N) { return lookup(P, N).lds; }
+
+size_t mgs_lds_limit() { return 80 * 1024; }
+
+void tune_set(int P, int N, int group, int lds) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table[{P, nbucket(N)}] = Choice{group, lds};
+}
+
+}  // namespace hcn
+
+using namespace hcn;
+
+extern "C" {
+
+int hcn_tune_set(int P, int N, int mgs_group, int mgs_lds) {
+    if ((P != 1 && P != 2 && P != 4) || N < 1 ||
+        (mgs_group != 8 && mgs_group != 16 && mgs_group != 32) || (mgs_lds != 0 && mgs_lds != 1))
+        return HCN_EINVAL;
+    tune_set(P, N, mgs_group, mgs_lds);
+    return HCN_OK;
+}
+
+int hcn_tune_get(int P, int N, int *mgs_group, int *mgs_lds) {
+    if (!mgs_group || !mgs_lds) return HCN_EINVAL;
+    *mgs_group = tune_mgs_group(P, N);
+    *mgs_lds = tune_mgs_lds(P, N);
+    return HCN_OK;
+}
+
+int hcn_tune_save(const char *path) {
+    if (!path) return HCN_EINVAL;
+    FILE *f = std::fopen(path, "w");
+    if (!f) return HCN_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &kv : g_table)
+        std::fprintf(f, "%d %d %d %d\n", kv.first.first, kv.first.second, kv.second.group,
+                     kv.second.lds);
+    std::fclose(f);
+    return HCN_OK;
+}
+
+int hcn_tune_load(const char *path) {
+    if (!path) return HCN_EINVAL;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return HCN_EINVAL;
+    int P, Nb, grp, lds, rc = HCN_OK;
+    while (std::fscanf(f, "%d %d %d %d", &P, &Nb, &grp, &lds) == 4)
+        if (hcn_tune_set(P, Nb, grp, lds) != HCN_OK) rc = HCN_EINVAL;
+    std::fclose(f);
+    return rc;
+}
+
+}  // extern "C"

@@ -64,6 +64,10 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
            "hcn_set_mgs_variant", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
+           "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load",
+           "hcn_batch_create", "hcn_batch_destroy", "hcn_batch_device_bytes",
+           "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_step",
+           "hcn_batch_poll", "hcn_batch_result", "hcn_batch_run",
            "hcn_profile_reset", "hcn_profile_query"]
 
 
@@ -98,6 +102,22 @@ def _load():
     lib.hcn_newton_mixed_ws_bytes.argtypes = [vp, ci]
     lib.hcn_newton_mixed_ws_bytes.restype = sz
     lib.hcn_newton_mixed.argtypes = lib.hcn_newton.argtypes
+    lib.hcn_tune_set.argtypes = [ci, ci, ci, ci]
+    lib.hcn_tune_get.argtypes = [ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    lib.hcn_tune_save.argtypes = [ctypes.c_char_p]
+    lib.hcn_tune_load.argtypes = [ctypes.c_char_p]
+    lib.hcn_batch_create.argtypes = [ctypes.POINTER(vp), ci, ci, ci, ci, ci,
+                                     ctypes.POINTER(_TrackParams), ci]
+    lib.hcn_batch_destroy.argtypes = [vp]
+    lib.hcn_batch_device_bytes.argtypes = [vp]
+    lib.hcn_batch_device_bytes.restype = sz
+    lib.hcn_batch_last_error.restype = ctypes.c_char_p
+    lib.hcn_batch_add.argtypes = [vp, ci, vp, vp, vp, vp]
+    lib.hcn_batch_release.argtypes = [vp, ci]
+    lib.hcn_batch_step.argtypes = [vp, ci, vp]
+    lib.hcn_batch_poll.argtypes = [vp, vp, vp]
+    lib.hcn_batch_result.argtypes = [vp, ci, vp, vp, vp]
+    lib.hcn_batch_run.argtypes = [vp, ci, vp]
     lib.hcn_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(cd),
                                       ctypes.POINTER(ctypes.c_int64)]
     return lib
@@ -355,3 +375,90 @@ MGS_AUTO, MGS_WORKGROUP, MGS_RIGHT_LOOKING, MGS_COLUMN_RESIDENT = 0, 1, 2, 3
 def set_mgs_variant(variant: int) -> None:
     """Process-wide MGS variant (see hcn_set_mgs_variant)."""
     _check(_lib.hcn_set_mgs_variant(int(variant)))
+
+
+def tune_set(P: int, N: int, mgs_group: int, mgs_lds: int) -> None:
+    """Kernel-variant choice for problems of precision P and N rows."""
+    _check(_lib.hcn_tune_set(P, N, mgs_group, mgs_lds))
+
+
+def tune_get(P: int, N: int):
+    g, l = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.hcn_tune_get(P, N, ctypes.byref(g), ctypes.byref(l)))
+    return g.value, l.value
+
+
+def _bcheck(rc: int) -> int:
+    if rc < 0:
+        raise HcnError(rc, _lib.hcn_batch_last_error().decode())
+    return rc
+
+
+def track_params(P: int, **kw) -> _TrackParams:
+    p = dict(DEFAULT_TRACK)
+    p.update(kw)
+    if p["end_tol"] is None:
+        p["end_tol"] = 1e-28 if P == 2 else 1e-58
+    return _TrackParams(int(p["max_iter"]), float(p["tol_res"]), float(p["tol_dx"]),
+                        float(p["max_eq_val"]), float(p["max_dt"]), float(p["min_dt"]),
+                        int(p["max_steps"]), int(p["end_iters"]), float(p["end_tol"]),
+                        int(p["predictor_order"]))
+
+
+class Batch:
+    """Slot table of paths of many systems (hcn_batch_*)."""
+
+    def __init__(self, P: int, capacity: int, max_n: int, max_nslots: int,
+                 max_systems: int = 256, relax_k: int = 1, **track_kw):
+        self.P = P
+        self.capacity = capacity
+        self.prm = track_params(P, **track_kw)
+        h = ctypes.c_void_p()
+        _bcheck(_lib.hcn_batch_create(ctypes.byref(h), P, capacity, max_n, max_nslots,
+                                      max_systems, ctypes.byref(self.prm), relax_k))
+        self.handle = h
+        self._keep = {}
+        self.device = torch.device("cuda", torch.cuda.current_device())
+
+    def add(self, slot: int, sys: System, gamma, x0: torch.Tensor):
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(2, self.P))
+        x0 = x0.contiguous()
+        self._keep[slot] = (sys, x0)
+        _bcheck(_lib.hcn_batch_add(self.handle, slot, sys.handle, _np_ptr(g), _ptr(x0), _stream()))
+
+    def release(self, slot: int):
+        self._keep.pop(slot, None)
+        _bcheck(_lib.hcn_batch_release(self.handle, slot))
+
+    def step(self, steps: int = 1):
+        _bcheck(_lib.hcn_batch_step(self.handle, steps, _stream()))
+
+    def poll(self):
+        """(number of unfinished occupied slots, done flags [capacity])."""
+        done = np.zeros(self.capacity, dtype=np.int32)
+        n = _bcheck(_lib.hcn_batch_poll(self.handle, _np_ptr(done), _stream()))
+        return n, done
+
+    def result(self, slot: int, n: int):
+        x = torch.empty((n, 2, self.P), dtype=torch.float64, device=self.device)
+        res = np.zeros(1, dtype=PATH_RESULT_DTYPE)
+        _bcheck(_lib.hcn_batch_result(self.handle, slot, _ptr(x), _np_ptr(res), _stream()))
+        return x, res[0]
+
+    def run(self, chunk: int = 8):
+        _bcheck(_lib.hcn_batch_run(self.handle, chunk, _stream()))
+
+    def device_bytes(self) -> int:
+        return int(_lib.hcn_batch_device_bytes(self.handle))
+
+    def free(self):
+        if self.handle:
+            _lib.hcn_batch_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -507,3 +507,123 @@ def test_mixed_newton_fig2_branches(H):
     st, it, nr = H.newton(sysd, xd, max_iter=1, tol_res=1e-300, tol_dx=1e-300,
                           max_eq_val=1e300, mixed=True)
     assert np.all(host(st) == H.NOT_CONVERGED) and np.all(host(it) == 1)
+
+
+# ---------------------------------------------------------------------------
+# kernel variants from the tuning table
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_tuned_variants(H, P):
+    """LDS staging does not change a bit; other lane-group widths stay within
+    the solve tolerance of the oracle."""
+    ps = S.dense32_system(0, P)
+    xs = S.dense32_points(3, 2, P)
+    sysd = H.System(ps)
+    out = {}
+    try:
+        for grp in (8, 16, 32):
+            for lds in (0, 1):
+                H.tune_set(P, ps.N, grp, lds)
+                xd = dev(xs)
+                _, status = H.newton_step(sysd, xd)
+                assert np.all(host(status) == 0)
+                out[(grp, lds)] = host(xd)
+    finally:
+        H.tune_set(P, ps.N, 16, 1)
+    for grp in (8, 16, 32):
+        assert _bitwise_equal(out[(grp, 0)], out[(grp, 1)])
+    for q in range(2):
+        rc, xo, no = O.newton_step(ps, None, None, 1, 1.0, xs[q])
+        kappa = _kappa_at(ps, xs[q])
+        tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
+        for grp in (8, 32):
+            assert np.abs(limb_diff(out[(grp, 1)][q], xo)).max() <= tol * no[1]
+
+
+# ---------------------------------------------------------------------------
+# slot-table batches of many systems
+# ---------------------------------------------------------------------------
+
+def _batch_cases(P):
+    """(system, gamma, start point) for paths of several different systems."""
+    cases = []
+    for seed in (3, 5, 6):
+        ps = S.small_track_system(seed, P)
+        rng = S.rng_for(0, 100 + seed)
+        gam = S.random_unit_gamma(rng, P)
+        cases.append((ps, gam, S.ones_point(ps.n, P)))
+    rng = S.rng_for(6, 11)
+    cs = S.unit_complex(rng.uniform(0, 6.28, 5), P)
+    ps = S.diagonal_power_system(cs, 3, P)
+    gam = S.random_unit_gamma(rng, P)
+    for _ in range(2):
+        cases.append((ps, gam, S.start_solution(rng, np.full(5, 3), P)))
+    return cases
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_batch_matches_single_system_tracking(H, P):
+    """Paths of several systems in one batch give bitwise the results of
+    tracking each system on its own, alone or in any mix."""
+    cases = _batch_cases(P)
+    systems = {}
+    for ps, _, _ in cases:
+        if id(ps) not in systems:
+            systems[id(ps)] = H.System(ps)
+    # each path alone through the single-system tracker
+    ref = []
+    for ps, gam, x0 in cases:
+        xo, res = H.track_paths(systems[id(ps)], gam, dev(x0[None]))
+        ref.append((host(xo)[0], res[0]))
+    maxs = max(systems[id(ps)].info().nslots for ps, _, _ in cases)
+    bt = H.Batch(P, capacity=8, max_n=8, max_nslots=maxs)
+    slots = [0, 2, 3, 5, 7]
+    for slot, (ps, gam, x0) in zip(slots, cases):
+        bt.add(slot, systems[id(ps)], gam, dev(x0))
+    bt.run()
+    n, done = bt.poll()
+    assert n == 0 and all(done[s] == 1 for s in slots)
+    for slot, (ps, gam, x0), (xr, rr) in zip(slots, cases, ref):
+        x, r = bt.result(slot, ps.n)
+        assert _bitwise_equal(host(x), xr)
+        assert r.tobytes() == rr.tobytes()
+    # a released slot takes a new path; the old paths are unaffected
+    bt.release(2)
+    ps, gam, x0 = cases[0]
+    bt.add(2, systems[id(ps)], gam, dev(x0))
+    bt.run()
+    x, r = bt.result(2, ps.n)
+    assert _bitwise_equal(host(x), ref[0][0]) and r.tobytes() == ref[0][1].tobytes()
+    # one path alone in a batch
+    bt2 = H.Batch(P, capacity=2, max_n=8, max_nslots=maxs)
+    ps, gam, x0 = cases[3]
+    bt2.add(1, systems[id(ps)], gam, dev(x0))
+    bt2.run()
+    x, r = bt2.result(1, ps.n)
+    assert _bitwise_equal(host(x), ref[3][0]) and r.tobytes() == ref[3][1].tobytes()
+    bt.free()
+    bt2.free()
+
+
+def test_batch_step_by_step_polling(H):
+    """Stepping a few steps at a time and polling reports progress."""
+    P = 2
+    cases = _batch_cases(P)[:3]
+    systems = [H.System(ps) for ps, _, _ in cases]
+    maxs = max(s.info().nslots for s in systems)
+    bt = H.Batch(P, capacity=4, max_n=8, max_nslots=maxs)
+    for slot, ((ps, gam, x0), sd) in enumerate(zip(cases, systems)):
+        bt.add(slot, sd, gam, dev(x0))
+    n0, _ = bt.poll()
+    assert n0 == 3
+    bt.step(2)
+    n1, done = bt.poll()
+    assert n1 == 3 and not done.any()
+    bt.run(chunk=16)
+    n2, done = bt.poll()
+    assert n2 == 0 and done[:3].all() and not done[3]
+    for slot, (ps, gam, x0) in enumerate(cases):
+        _, r = bt.result(slot, ps.n)
+        xo, ro = O.track(ps, O.total_degree_start(ps), gam, 1, x0)
+        assert (r["status"], r["steps"], r["accepted"]) == (ro.status, ro.steps, ro.accepted)
