@@ -193,7 +193,11 @@ struct hcn_batch_s {
     int32_t *h_running = nullptr, *h_done = nullptr;
     bool dirty = true;
     hipGraphExec_t exec = nullptr;
-    hipStream_t exec_stream = nullptr;
+    // graphs are captured and replayed on the batch's own stream (capture is
+    // not possible on the legacy null stream), joined to the caller's stream
+    // with events on both sides
+    hipStream_t own = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
 
 extern "C" const char *hcn_batch_last_error(void) { return g_berr.c_str(); }
@@ -393,6 +397,15 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
         delete b;
         return bfail(HCN_ENOMEM, "hcn_batch_create: pinned allocation failed");
     }
+    if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(b->h_running);
+        (void)hipHostFree(b->h_done);
+        (void)hipFree(b->dmem);
+        delete b;
+        return bfail(HCN_EDEVICE, "hcn_batch_create: stream or event creation failed");
+    }
     if (P == 2)
         set_lds_attributes<dd>();
     else
@@ -403,7 +416,11 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
 
 int hcn_batch_destroy(hcn_batch b) {
     if (!b) return HCN_OK;
+    if (b->own) (void)hipStreamSynchronize(b->own);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->own) (void)hipStreamDestroy(b->own);
     (void)hipHostFree(b->h_running);
     (void)hipHostFree(b->h_done);
     (void)hipFree(b->dmem);
@@ -473,25 +490,28 @@ int hcn_batch_step(hcn_batch b, int steps, void *stream) {
         if (rc) return rc;
     }
     if (b->n_slots == 0 || steps == 0) return HCN_OK;
-    if (!b->exec || b->exec_stream != s) {
-        if (b->exec) {
-            (void)hipGraphExecDestroy(b->exec);
-            b->exec = nullptr;
-        }
+    hipStream_t own = b->own;
+    if (!b->exec) {
         hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        if (hipStreamBeginCapture(own, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return bfail(HCN_EDEVICE, "hcn_batch_step: capture begin failed");
-        const int e = b->P == 2 ? enqueue_step<dd>(b, s) : enqueue_step<qd>(b, s);
-        const hipError_t ec = hipStreamEndCapture(s, &g);
+        const int e = b->P == 2 ? enqueue_step<dd>(b, own) : enqueue_step<qd>(b, own);
+        const hipError_t ec = hipStreamEndCapture(own, &g);
         if (e || ec != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_step: capture failed");
         const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ei != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_step: instantiate failed");
-        b->exec_stream = s;
     }
-    ProfScope prof("batch_step", s);
-    for (int q = 0; q < steps; ++q)
-        if (hipGraphLaunch(b->exec, s) != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_step: graph launch failed");
+    if (hipEventRecord(b->ev_in, s) != hipSuccess || hipStreamWaitEvent(own, b->ev_in, 0) != hipSuccess)
+        return bfail(HCN_EDEVICE, "hcn_batch_step: stream join failed");
+    {
+        ProfScope prof("batch_step", own);
+        for (int q = 0; q < steps; ++q)
+            if (hipGraphLaunch(b->exec, own) != hipSuccess)
+                return bfail(HCN_EDEVICE, "hcn_batch_step: graph launch failed");
+    }
+    if (hipEventRecord(b->ev_out, own) != hipSuccess || hipStreamWaitEvent(s, b->ev_out, 0) != hipSuccess)
+        return bfail(HCN_EDEVICE, "hcn_batch_step: stream join failed");
     return HCN_OK;
 }
 
