@@ -263,8 +263,13 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B,
 
 typedef struct hcn_batch_s *hcn_batch;
 
+/* flags: HCN_BATCH_MIXED runs every corrector iteration in mixed precision
+ * (residual and update in DD/QD, Jacobian and MGS in FP64, as
+ * hcn_newton_mixed). */
+#define HCN_BATCH_MIXED 1
+
 int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nslots,
-                     int max_systems, const hcn_track_params *prm, int relax_k);
+                     int max_systems, const hcn_track_params *prm, int relax_k, int flags);
 int hcn_batch_destroy(hcn_batch b);
 size_t hcn_batch_device_bytes(hcn_batch b);
 const char *hcn_batch_last_error(void);

@@ -28,6 +28,7 @@ namespace hcn {
 
 struct BatchDev {
     int P, max_n, max_nparts, relax_k;
+    int mixed;            // FP64 Jacobian and solve, DD/QD residual and update
     const SysView *sys;   // registry
     const int *slot_sys;  // [cap] registry index, -1 empty
     const int *slot_lds;  // [cap] stage [A | b] in LDS
@@ -77,9 +78,15 @@ __global__ __launch_bounds__(256) void k_b_mon(BatchDev d, const int2 *work) {
     mon_one<R, KB, MODE>(s, m, d.x + (size_t)slot * d.xs, d.P, d.sc + (size_t)slot * d.scs);
 }
 
-template <class R>
+// what a sum launch forms: the full [J | -h] with its norm parts, the
+// residual only (rounded -h into the FP64 matrix, with norm parts), or the
+// FP64 Jacobian only
+enum { BSUM_FULL = 0, BSUM_RESIDUAL = 1, BSUM_JACOBIAN = 2 };
+
+template <class R, int VARIANT>
 __global__ __launch_bounds__(256) void k_b_sum(BatchDev d, const int2 *work) {
     constexpr int W = 2 * limbs<R>::P;
+    constexpr int WJ = VARIANT == BSUM_RESIDUAL ? 2 : W;  // element width of the matrix
     __shared__ double red[256 / 64];
     const int2 w = work[blockIdx.x];
     const int slot = w.x;
@@ -87,17 +94,59 @@ __global__ __launch_bounds__(256) void k_b_sum(BatchDev d, const int2 *work) {
     const SysView &s = d.sys[d.slot_sys[slot]];
     double *J = d.J + (size_t)slot * d.Js;
     SumOut o;
-    o.jac = 1;
-    o.J = J;
-    o.J_cstride = (long)s.N * W;
-    o.f = J + (size_t)s.n * s.N * W;
+    o.jac = VARIANT == BSUM_RESIDUAL ? 0 : 1;
+    o.J = VARIANT == BSUM_RESIDUAL ? nullptr : J;
+    o.J_cstride = (long)s.N * WJ;
+    o.f = VARIANT == BSUM_JACOBIAN ? nullptr : J + (size_t)s.n * s.N * WJ;
     o.f_neg = 1;
-    o.f_lead_only = 0;
+    o.f_lead_only = VARIANT == BSUM_RESIDUAL ? 1 : 0;
     const long e = (long)w.y * 256 + threadIdx.x;
     const double mx = sum_one<R>(s, e, d.sc + (size_t)slot * d.scs, d.x + (size_t)slot * d.xs, d.P,
-                                 1, d.relax_k, d.t[slot], d.gamma + (size_t)slot * W, d.P, o);
+                                 1, d.relax_k, d.t[slot], d.gamma + (size_t)slot * 2 * d.P, d.P, o);
+    if (VARIANT == BSUM_JACOBIAN) return;
     const double r = block_max(mx, red);
     if (threadIdx.x == 0) d.np[(size_t)slot * d.nps + w.y] = r;
+}
+
+__global__ void k_b_fig2_pre(BatchDev d, const int *slots, int count) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const int slot = slots[q];
+    const SysView &s = d.sys[d.slot_sys[slot]];
+    MgsProblem p = {};
+    p.norm_part = d.np + (size_t)slot * d.nps;
+    p.nparts = (s.N + 255) / 256;
+    p.st = d.st + slot;
+    (void)fig2_decide(p);
+}
+
+template <class Rx>
+__global__ __launch_bounds__(MGS_THREADS) void k_b_mixed_update(BatchDev d, const int *slots) {
+    constexpr int Wx = 2 * limbs<Rx>::P;
+    __shared__ double s_red[MGS_THREADS / 64];
+    const int slot = slots[blockIdx.x];
+    PathState &st = d.st[slot];
+    if (!st.c_active) return;
+    const int n = d.sys[d.slot_sys[slot]].n;
+    const double *dx = d.sc + (size_t)slot * d.scs;
+    double *x = d.x + (size_t)slot * d.xs;
+    double m = 0.0;
+    for (int i = threadIdx.x; i < n; i += MGS_THREADS)
+        m = nanmax(m, nanmax(fabs(dx[2 * i]), fabs(dx[2 * i + 1])));
+    for (int off = 32; off >= 1; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    double dxn = s_red[0];
+    for (int w = 1; w < MGS_THREADS / 64; ++w) dxn = nanmax(dxn, s_red[w]);
+    if (dxn == dxn) {
+        for (int i = threadIdx.x; i < n; i += MGS_THREADS) {
+            double *q = x + (size_t)i * Wx;
+            const cx<double> dd{dx[2 * i], dx[2 * i + 1]};
+            cstore(q, cadd(cload<Rx>(q), cwiden<Rx>(dd)));
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) fig2_after_update(st, dxn);
 }
 
 template <class R, int GRP>
@@ -108,7 +157,7 @@ __global__ __launch_bounds__(MGS_THREADS) void k_b_mgs(BatchDev d, const int *sl
     MgsProblem p;
     p.N = s.N;
     p.n = s.n;
-    p.mode = MGS_NEWTON_FIG2;
+    p.mode = d.mixed ? MGS_MIXED_SOLVE : MGS_NEWTON_FIG2;
     p.lds = d.slot_lds[slot];
     p.A = d.J + (size_t)slot * d.Js;
     p.A_cstride = (long)s.N * W;
@@ -183,9 +232,9 @@ struct hcn_batch_s {
     std::vector<int> slot_sys, slot_lds;
     int *d_slot_sys = nullptr, *d_slot_lds = nullptr;
     // work lists
-    int2 *d_mon = nullptr, *d_sum = nullptr;
+    int2 *d_mon = nullptr, *d_sum = nullptr, *d_sumf = nullptr;
     int *d_slots = nullptr;
-    int n_mon = 0, n_sum = 0, n_slots = 0;
+    int n_mon = 0, n_sum = 0, n_sumf = 0, n_slots = 0;
     int grp_off[3] = {0, 0, 0}, grp_cnt[3] = {0, 0, 0};
     size_t grp_lds[3] = {0, 0, 0};
     long mon_cap = 0, sum_cap = 0;
@@ -204,6 +253,34 @@ extern "C" const char *hcn_batch_last_error(void) { return g_berr.c_str(); }
 
 namespace {
 
+template <class R, int MODE>
+void launch_b_mon(hcn_batch_s *b, hipStream_t s) {
+    const BatchDev &d = b->d;
+    switch (b->kb) {
+        case 4: hipLaunchKernelGGL((k_b_mon<R, 4, MODE>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+        case 8: hipLaunchKernelGGL((k_b_mon<R, 8, MODE>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+        case 16: hipLaunchKernelGGL((k_b_mon<R, 16, MODE>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+        case 32: hipLaunchKernelGGL((k_b_mon<R, 32, MODE == MON_VALUES ? MON_VALUES : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+        default: hipLaunchKernelGGL((k_b_mon<R, 64, MODE == MON_VALUES ? MON_VALUES : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+    }
+}
+
+template <class R>
+void launch_b_mgs(hcn_batch_s *b, hipStream_t s) {
+    const BatchDev &d = b->d;
+    const int grps[3] = {8, 16, 32};
+    for (int g = 0; g < 3; ++g) {
+        if (b->grp_cnt[g] == 0) continue;
+        const int *list = b->d_slots + b->grp_off[g];
+        const size_t lds = b->grp_lds[g];
+        switch (grps[g]) {
+            case 8: hipLaunchKernelGGL((k_b_mgs<R, 8>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
+            case 16: hipLaunchKernelGGL((k_b_mgs<R, 16>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
+            default: hipLaunchKernelGGL((k_b_mgs<R, 32>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
+        }
+    }
+}
+
 template <class R>
 int enqueue_step(hcn_batch_s *b, hipStream_t s) {
     const BatchDev &d = b->d;
@@ -211,24 +288,21 @@ int enqueue_step(hcn_batch_s *b, hipStream_t s) {
     hipLaunchKernelGGL(k_b_begin<R>, dim3(b->n_slots), dim3(64), 0, s, d, b->d_slots);
     constexpr bool isdd = limbs<R>::P == 2;
     for (int it = 0; it < d.prm.max_iter; ++it) {
-        switch (b->kb) {
-            case 4: hipLaunchKernelGGL((k_b_mon<R, 4, isdd ? MON_FREG : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
-            case 8: hipLaunchKernelGGL((k_b_mon<R, 8, isdd ? MON_FREG : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
-            case 16: hipLaunchKernelGGL((k_b_mon<R, 16, isdd ? MON_FREG : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
-            case 32: hipLaunchKernelGGL((k_b_mon<R, 32, MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
-            default: hipLaunchKernelGGL((k_b_mon<R, 64, MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
-        }
-        hipLaunchKernelGGL(k_b_sum<R>, dim3(b->n_sum), dim3(256), 0, s, d, b->d_sum);
-        const int grps[3] = {8, 16, 32};
-        for (int g = 0; g < 3; ++g) {
-            if (b->grp_cnt[g] == 0) continue;
-            const int *list = b->d_slots + b->grp_off[g];
-            const size_t lds = b->grp_lds[g];
-            switch (grps[g]) {
-                case 8: hipLaunchKernelGGL((k_b_mgs<R, 8>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
-                case 16: hipLaunchKernelGGL((k_b_mgs<R, 16>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
-                default: hipLaunchKernelGGL((k_b_mgs<R, 32>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
-            }
+        if (!d.mixed) {
+            launch_b_mon<R, isdd ? MON_FREG : MON_FSLOT>(b, s);
+            hipLaunchKernelGGL((k_b_sum<R, BSUM_FULL>), dim3(b->n_sum), dim3(256), 0, s, d, b->d_sum);
+            launch_b_mgs<R>(b, s);
+        } else {
+            // residual in DD/QD, its rounding the right-hand side; Fig. 2 tests
+            launch_b_mon<R, MON_VALUES>(b, s);
+            hipLaunchKernelGGL((k_b_sum<R, BSUM_RESIDUAL>), dim3(b->n_sumf), dim3(256), 0, s, d, b->d_sumf);
+            hipLaunchKernelGGL(k_b_fig2_pre, dim3((b->n_slots + 255) / 256), dim3(256), 0, s, d,
+                               b->d_slots, b->n_slots);
+            // Jacobian and solve in FP64, update in DD/QD
+            launch_b_mon<double, MON_FREG>(b, s);
+            hipLaunchKernelGGL((k_b_sum<double, BSUM_JACOBIAN>), dim3(b->n_sum), dim3(256), 0, s, d, b->d_sum);
+            launch_b_mgs<double>(b, s);
+            hipLaunchKernelGGL(k_b_mixed_update<R>, dim3(b->n_slots), dim3(MGS_THREADS), 0, s, d, b->d_slots);
         }
     }
     hipLaunchKernelGGL(k_b_end<R>, dim3(b->n_slots), dim3(64), 0, s, d, b->d_slots);
@@ -245,8 +319,9 @@ void set_lds_attributes() {
 
 // work lists from the occupied slots; slots grouped by MGS lane-group width
 int rebuild(hcn_batch_s *b) {
-    std::vector<int2> mon, sum;
+    std::vector<int2> mon, sum, sumf;
     std::vector<int> lists[3];
+    const int Ps = b->d.mixed ? 1 : b->P;  // precision of the solve
     const int grps[3] = {8, 16, 32};
     size_t lds_need[3] = {0, 0, 0};
     for (int s = 0; s < b->cap; ++s) {
@@ -256,11 +331,13 @@ int rebuild(hcn_batch_s *b) {
         for (int q = 0; q < mb; ++q) mon.push_back(make_int2(s, q));
         const int sb = sum_nparts(v, 1);
         for (int q = 0; q < sb; ++q) sum.push_back(make_int2(s, q));
-        const int grp = tune_mgs_group(b->P, v.N);
+        const int sf = sum_nparts(v, 0);
+        for (int q = 0; q < sf; ++q) sumf.push_back(make_int2(s, q));
+        const int grp = tune_mgs_group(Ps, v.N);
         const int g = grp == 8 ? 0 : grp == 32 ? 2 : 1;
         lists[g].push_back(s);
-        const size_t bytes = mgs_lds_bytes(v.N, v.n, b->P);
-        const int lds = (bytes <= mgs_lds_limit() && tune_mgs_lds(b->P, v.N)) ? 1 : 0;
+        const size_t bytes = mgs_lds_bytes(v.N, v.n, Ps);
+        const int lds = (bytes <= mgs_lds_limit() && tune_mgs_lds(Ps, v.N)) ? 1 : 0;
         b->slot_lds[s] = lds;
         if (lds) lds_need[g] = std::max(lds_need[g], bytes);
         (void)grps;
@@ -274,12 +351,14 @@ int rebuild(hcn_batch_s *b) {
     }
     b->n_mon = (int)mon.size();
     b->n_sum = (int)sum.size();
+    b->n_sumf = (int)sumf.size();
     b->n_slots = (int)slots.size();
     if ((long)mon.size() > b->mon_cap || (long)sum.size() > b->sum_cap)
         return bfail(HCN_EINVAL, "hcn_batch: work list exceeds its capacity");
     hipError_t e = hipSuccess;
     if (!mon.empty()) e = hipMemcpy(b->d_mon, mon.data(), mon.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (!e && !sum.empty()) e = hipMemcpy(b->d_sum, sum.data(), sum.size() * sizeof(int2), hipMemcpyHostToDevice);
+    if (!e && !sumf.empty()) e = hipMemcpy(b->d_sumf, sumf.data(), sumf.size() * sizeof(int2), hipMemcpyHostToDevice);
     if (!e && !slots.empty()) e = hipMemcpy(b->d_slots, slots.data(), slots.size() * sizeof(int), hipMemcpyHostToDevice);
     if (!e) e = hipMemcpy(b->d_slot_sys, b->slot_sys.data(), b->cap * sizeof(int), hipMemcpyHostToDevice);
     if (!e) e = hipMemcpy(b->d_slot_lds, b->slot_lds.data(), b->cap * sizeof(int), hipMemcpyHostToDevice);
@@ -297,7 +376,7 @@ int rebuild(hcn_batch_s *b) {
 extern "C" {
 
 int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nslots,
-                     int max_systems, const hcn_track_params *prm, int relax_k) {
+                     int max_systems, const hcn_track_params *prm, int relax_k, int flags) {
     if (!out || !prm) return bfail(HCN_EINVAL, "hcn_batch_create: NULL argument");
     *out = nullptr;
     if ((P != 2 && P != 4) || capacity < 1 || max_n < 1 || max_n > 1024 || max_nslots < 1 ||
@@ -334,7 +413,8 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
                  o_t = take(cap * 8), o_g = take(cap * W * 8), o_st = take(cap * sizeof(PathState)),
                  o_res = take(cap * sizeof(hcn_path_result)), o_sys = take(max_systems * sizeof(SysView)),
                  o_ss = take(cap * 4), o_sl = take(cap * 4), o_mon = take(b->mon_cap * sizeof(int2)),
-                 o_sum = take(b->sum_cap * sizeof(int2)), o_slots = take(cap * 4), o_done = take(cap * 4),
+                 o_sum = take(b->sum_cap * sizeof(int2)), o_sumf = take(cap * ((max_n + 255) / 256) * sizeof(int2)),
+                 o_slots = take(cap * 4), o_done = take(cap * 4),
                  o_run = take(4);
     b->bytes = off;
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
@@ -346,6 +426,7 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
     d.P = P;
     d.max_n = max_n;
     d.relax_k = relax_k;
+    d.mixed = (flags & HCN_BATCH_MIXED) ? 1 : 0;
     d.x = (double *)(base + o_x);
     d.x_acc = (double *)(base + o_xa);
     d.x_prev = (double *)(base + o_xp);
@@ -371,6 +452,7 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
     b->d_slot_lds = (int *)(base + o_sl);
     b->d_mon = (int2 *)(base + o_mon);
     b->d_sum = (int2 *)(base + o_sum);
+    b->d_sumf = (int2 *)(base + o_sumf);
     b->d_slots = (int *)(base + o_slots);
     b->d_done = (int32_t *)(base + o_done);
     b->d_running = (int32_t *)(base + o_run);
@@ -410,6 +492,7 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
         set_lds_attributes<dd>();
     else
         set_lds_attributes<qd>();
+    set_lds_attributes<double>();
     *out = b;
     return HCN_OK;
 }

@@ -107,7 +107,7 @@ def _load():
     lib.hcn_tune_save.argtypes = [ctypes.c_char_p]
     lib.hcn_tune_load.argtypes = [ctypes.c_char_p]
     lib.hcn_batch_create.argtypes = [ctypes.POINTER(vp), ci, ci, ci, ci, ci,
-                                     ctypes.POINTER(_TrackParams), ci]
+                                     ctypes.POINTER(_TrackParams), ci, ci]
     lib.hcn_batch_destroy.argtypes = [vp]
     lib.hcn_batch_device_bytes.argtypes = [vp]
     lib.hcn_batch_device_bytes.restype = sz
@@ -409,13 +409,14 @@ class Batch:
     """Slot table of paths of many systems (hcn_batch_*)."""
 
     def __init__(self, P: int, capacity: int, max_n: int, max_nslots: int,
-                 max_systems: int = 256, relax_k: int = 1, **track_kw):
+                 max_systems: int = 256, relax_k: int = 1, mixed: bool = False, **track_kw):
         self.P = P
         self.capacity = capacity
         self.prm = track_params(P, **track_kw)
         h = ctypes.c_void_p()
         _bcheck(_lib.hcn_batch_create(ctypes.byref(h), P, capacity, max_n, max_nslots,
-                                      max_systems, ctypes.byref(self.prm), relax_k))
+                                      max_systems, ctypes.byref(self.prm), relax_k,
+                                      1 if mixed else 0))
         self.handle = h
         self._keep = {}
         self.device = torch.device("cuda", torch.cuda.current_device())

@@ -627,3 +627,37 @@ def test_batch_step_by_step_polling(H):
         _, r = bt.result(slot, ps.n)
         xo, ro = O.track(ps, O.total_degree_start(ps), gam, 1, x0)
         assert (r["status"], r["steps"], r["accepted"]) == (ro.status, ro.steps, ro.accepted)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_batch_mixed_precision_tracking(H, P):
+    """The mixed-precision corrector (FP64 Jacobian and MGS, DD/QD residual
+    and update) tracks to the same endpoints as the plain one, refined to
+    the DD/QD tolerance, and the endpoints are roots at 320 bits."""
+    cases = _batch_cases(P)
+    systems = {}
+    for ps, _, _ in cases:
+        if id(ps) not in systems:
+            systems[id(ps)] = H.System(ps)
+    maxs = max(systems[id(ps)].info().nslots for ps, _, _ in cases)
+    out = {}
+    for mixed in (False, True):
+        bt = H.Batch(P, capacity=len(cases), max_n=8, max_nslots=maxs, mixed=mixed)
+        for slot, (ps, gam, x0) in enumerate(cases):
+            bt.add(slot, systems[id(ps)], gam, dev(x0))
+        bt.run()
+        out[mixed] = [bt.result(slot, ps.n) for slot, (ps, _, _) in enumerate(cases)]
+        bt.free()
+    ok = 0
+    for q, (ps, gam, x0) in enumerate(cases):
+        (xp, rp), (xm, rm) = out[False][q], out[True][q]
+        if rp["status"] != H.OK or rp["end_status"] != H.OK:
+            continue
+        assert rm["status"] == H.OK and rm["end_status"] == H.OK, (q, rm)
+        xp, xm = host(xp), host(xm)
+        scale = max(1.0, np.abs(lead_complex(xp)).max())
+        assert np.abs(limb_diff(xm, xp)).max() <= 100 * GATE[P] * scale
+        fv, _ = M.eval_system(ps, M.vec(xm))
+        assert max(abs(v) for v in fv) <= 100 * GATE[P] * scale ** 6
+        ok += 1
+    assert ok >= 3
