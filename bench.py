@@ -89,6 +89,7 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single"))
         sysd = hcn.System(ps)
         x0 = torch.from_numpy(pts).to(dev)
         x = torch.empty_like(x0)
+        tuned = hcn.autotune(sysd, x0, reps=3) if B > 1 else None
         ws = hcn.newton_ws(sysd, B)
         for _ in range(W):
             x.copy_(x0)
@@ -119,7 +120,7 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single"))
         ok = int((status == 0).sum().item())
         fl = flops.newton_step(ps, P)
         sysd.free()
-        return dict(ms_per_step=ev_ms / K, wall_s=wall, B=B, ok=ok, flops=fl, kern=kern)
+        return dict(ms_per_step=ev_ms / K, wall_s=wall, B=B, ok=ok, flops=fl, kern=kern, tuned=tuned)
 
     if "dd" in legs:
         out["dd"] = leg(2, B_DD, steps, warmup, profile=True)
@@ -130,7 +131,150 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single"))
         out["single"] = leg(2, 1, 200, 5, profile=False)
     if "sparse512" in legs:
         out["sparse512"] = sparse512_leg(hcn, flops, S, dev)
+    if "batch64" in legs:
+        out["batch64"] = batch_leg(hcn, flops, S, dev)
+    if "serve" in legs:
+        out["serve"] = serve_leg(hcn, S, dev)
     return out
+
+
+def serve_leg(hcn, S, dev, pool: int = 32, burst: int = 384, poisson: int = 384,
+              serial_sample: int = 12, max_steps: int = 400) -> dict:
+    """Continuous batching of track_path requests: systems drawn like the
+    batch systems but with n log-uniform in [8, 128]; each request picks a
+    system, DD (p = 0.8) or QD, a random total-degree start solution and
+    gamma.  Capacity: a burst of requests all arriving at once (paths/s).
+    Latency: Poisson arrivals at 0.8 x that capacity (p50/p99 of arrival to
+    result, queueing included).  Baseline: the same server admitting one
+    path at a time, on a sample.  Paths stop after max_steps steps (a
+    per-request budget; paths of these systems without a constant term
+    often diverge)."""
+    import numpy as np
+    dd_sys = S.batch_systems(pool, seed=5, P=2, n_range=(8, 128), log_uniform_n=True)
+    qd_sys = S.batch_systems(pool, seed=5, P=4, n_range=(8, 128), log_uniform_n=True)
+    loaded = {2: [hcn.System(ps) for ps in dd_sys], 4: [hcn.System(ps) for ps in qd_sys]}
+    max_n = max(ps.n for ps in dd_sys)
+    max_slots = max(s.info().nslots for s in loaded[4])
+    rng = np.random.Generator(np.random.PCG64(4000))
+
+    def make_requests(count):
+        reqs = []
+        for _ in range(count):
+            si = int(rng.integers(0, pool))
+            P = 4 if rng.random() < 0.2 else 2
+            ps = (qd_sys if P == 4 else dd_sys)[si]
+            x0 = S.start_solution(rng, S.degrees(ps), P)
+            gam = S.random_unit_gamma(rng, P)
+            reqs.append((P, si, gam, x0))
+        return reqs
+
+    def run(reqs, arrivals, serial=False):
+        srv = hcn.Server(int(48e9), max_n=max_n, max_nslots=max_slots, qd_share=0.2,
+                         steps_per_round=8, serial=serial, max_steps=max_steps)
+        t0 = srv.now()
+        nxt = 0
+        got = {}
+        while len(got) < len(reqs):
+            now = srv.now() - t0
+            while nxt < len(reqs) and arrivals[nxt] <= now:
+                P, si, gam, x0 = reqs[nxt]
+                srv.submit(nxt, loaded[P][si], gam, x0, t0 + arrivals[nxt])
+                nxt += 1
+            srv.pump()
+            while True:
+                r = srv.fetch()
+                if r is None:
+                    break
+                got[r[0]] = r
+        wall = srv.now() - t0
+        cap = srv.capacity()
+        srv.free()
+        lat = np.array([got[i][5] - got[i][3] for i in range(len(reqs))])
+        ok = sum(1 for i in range(len(reqs)) if got[i][2]["status"] == 0)
+        return {"requests": len(reqs), "wall_s": wall, "paths_per_s": len(reqs) / wall,
+                "p50_ms": 1e3 * float(np.percentile(lat, 50)),
+                "p99_ms": 1e3 * float(np.percentile(lat, 99)),
+                "succeeded": ok, "slots": {"dd": cap[0], "qd": cap[1]}}
+
+    reqs = make_requests(burst)
+    cap = run(reqs, np.zeros(burst))
+    lam = 0.8 * cap["paths_per_s"]
+    reqs2 = make_requests(poisson)
+    arr = np.cumsum(rng.exponential(1.0 / lam, size=poisson))
+    lat = run(reqs2, arr)
+    lat["rate_per_s"] = lam
+    sample = reqs2[:serial_sample]
+    base = run(sample, np.zeros(len(sample)), serial=True)
+    for s in loaded.values():
+        for q in s:
+            q.free()
+    return {"pool_systems": pool, "max_steps": max_steps, "capacity_burst": cap,
+            "poisson_0.8": lat, "one_at_a_time": base}
+
+
+def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10) -> dict:
+    """64 random systems (n in [16, 96], 16..64 monomials per equation, 4..12
+    variables per monomial, exponents 1..3), 64 total-degree start solutions
+    each: 4096 paths in one slot-table batch, tracked in complex DD for a
+    fixed number of predictor-corrector steps with the plain and with the
+    mixed-precision corrector.  Counts residual evaluations and solves per
+    path on the device; flops per path from its own system."""
+    import numpy as np
+    import torch
+    systems = S.batch_systems(nsys, seed=0, P=2)
+    loaded = [hcn.System(ps) for ps in systems]
+    infos = [s.info() for s in loaded]
+    max_n = max(ps.n for ps in systems)
+    max_slots = max(i.nslots for i in infos)
+    rng = S.rng_for(3, 777)
+    starts, gammas = [], []
+    for ps in systems:
+        degs = S.degrees(ps)
+        gammas.append(S.random_unit_gamma(rng, 2))
+        starts.append(torch.from_numpy(np.stack([S.start_solution(rng, degs, 2)
+                                                 for _ in range(per)])).to(dev))
+    fl_plain = [flops.newton_step(ps, 2) for ps in systems]
+    fl_mixed = [flops.mixed_step(ps, 2) for ps in systems]
+    res = {"systems": nsys, "paths": nsys * per, "timed_steps": steps}
+    for mode in ("plain", "mixed"):
+        bt = hcn.Batch(2, nsys * per, max_n, max_slots, max_systems=nsys, mixed=(mode == "mixed"))
+        for s in range(nsys):
+            for q in range(per):
+                bt.add(s * per + q, loaded[s], gammas[s], starts[s][q])
+        bt.step(2)
+        c0 = bt.counts()
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record()
+        bt.step(steps)
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop)
+        c1 = bt.counts()
+        d = (c1 - c0).astype(np.int64)
+        evals = int(d[:, 0].sum())
+        solves = int(d[:, 1].sum())
+        fl = 0.0
+        for s in range(nsys):
+            ev = d[s * per:(s + 1) * per, 0].sum()
+            so = d[s * per:(s + 1) * per, 1].sum()
+            if mode == "plain":
+                f = fl_plain[s]
+                fl += ev * (f["eval_monomials"] + f["eval_sums"]) + so * f["mgs"]
+            else:
+                f = fl_mixed[s]
+                fl += ev * f["residual"] + so * (f["jacobian"] + f["mgs"] + f["update"])
+        res[mode] = {"ms": ms, "evaluations": evals, "solves": solves,
+                     "newton_steps_per_s": solves / (ms / 1e3),
+                     "evaluations_per_s": evals / (ms / 1e3),
+                     "tflops": fl / (ms / 1e3) / 1e12,
+                     "pct_fp64_peak": 100.0 * fl / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS,
+                     "device_gb": bt.device_bytes() / 1e9}
+        bt.free()
+    for s in loaded:
+        s.free()
+    return res
 
 
 def sparse512_leg(hcn, flops, S, dev, reps: int = 10) -> dict:
@@ -182,7 +326,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--qd-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--legs", default="dd,qd,single,sparse512",
+    ap.add_argument("--legs", default="dd,qd,single,sparse512,batch64,serve",
                     help="comma list of dd (the reported line), qd, single; profiling runs use one")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -233,6 +377,7 @@ def main() -> int:
             "precision": "complex double-double",
             "points_per_step": dd["B"],
             "seed": 1000,
+            "mgs_variant": {"lane_group": dd["tuned"][0], "lds": dd["tuned"][1]} if dd["tuned"] else None,
         },
         "roofline": {
             "bound": "alu",
@@ -257,6 +402,8 @@ def main() -> int:
             (qd["ms_per_step"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS},
         "single_path_us_per_newton_step": None if single is None else single["ms_per_step"] * 1e3,
         "sparse512": r.get("sparse512"),
+        "batch64": r.get("batch64"),
+        "serve": r.get("serve"),
     }
     if rank == 0:
         print(json.dumps(line), flush=True)

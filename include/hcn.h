@@ -148,7 +148,7 @@ int hcn_set_mgs_variant(int variant);
 /* Kernel-variant table used by the one-workgroup MGS: lane-group width
  * (8, 16 or 32 lanes per column) and LDS staging (0/1) per precision P
  * (1 = the FP64 solve of the mixed-precision step, 2, 4) and row count N
- * (bucketed to the next power of two >= 8).  Defaults: 16, LDS on.  The
+ * (bucketed to the next power of two >= 8).  Defaults: 16, LDS off.  The
  * choice depends only on (P, N), so a problem's result does not depend on
  * the batch it is solved in.  save/load: text, one "P N group lds" line per
  * entry.  hcn_autotune (batch section) fills the table by timing. */
@@ -156,6 +156,13 @@ int hcn_tune_set(int P, int N, int mgs_group, int mgs_lds);
 int hcn_tune_get(int P, int N, int *mgs_group, int *mgs_lds);
 int hcn_tune_save(const char *path);
 int hcn_tune_load(const char *path);
+
+/* Autotuner: times hcn_newton_step of `sys` at the B points x_dev (device
+ * [B][n][2][P], left unchanged) for every lane-group width and LDS choice
+ * (reps steps each after a warm-up pass, HIP events on `stream`), stores the
+ * fastest in the table for (P, N) and returns it.  Synchronous. */
+int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_group,
+                 int *best_lds, double *best_ms, void *stream);
 
 /* ------------------------------------------------------------------------
  * Newton's method (equation (2); Fig. 2).  The system is either f alone
@@ -295,8 +302,50 @@ int hcn_batch_poll(hcn_batch b, int32_t *done_host, void *stream);
 int hcn_batch_result(hcn_batch b, int slot, double *x_out_dev, hcn_path_result *res_host,
                      void *stream);
 
+/* Work done so far per slot: counts_host [capacity][2] = residual
+ * evaluations and linear solves since the slot's path started (0 for empty
+ * slots).  Waits for the stream. */
+int hcn_batch_counts(hcn_batch b, int32_t *counts_host, void *stream);
+
 /* Step every occupied slot to the end, polling after every `chunk` steps. */
 int hcn_batch_run(hcn_batch b, int chunk, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of path-tracking requests of many systems
+ * and two precisions.  One slot-table batch per precision; its slot count
+ * is its share of budget_bytes (qd_share for QD) divided by the device
+ * footprint of one slot sized for systems with N == n <= max_n and at most
+ * max_nslots evaluation slots, so requests are admitted by device-memory
+ * footprint: a request waits in its precision's FIFO queue until a slot is
+ * free.  hcn_server_pump harvests finished paths, admits queued requests
+ * and advances every path by steps_per_round steps; requests admitted
+ * while others run join the same launches, and a result does not depend on
+ * the mix.  serial != 0 runs one path at a time (a baseline).  Times are
+ * seconds on the server's monotonic clock (hcn_server_now).
+ * --------------------------------------------------------------------- */
+
+typedef struct hcn_server_s *hcn_server;
+
+int hcn_server_create(hcn_server *out, size_t budget_bytes, double qd_share, int max_n,
+                      int max_nslots, const hcn_track_params *dd_prm,
+                      const hcn_track_params *qd_prm, int steps_per_round, int serial);
+int hcn_server_destroy(hcn_server s);
+const char *hcn_server_last_error(void);
+double hcn_server_now(hcn_server s);
+int hcn_server_capacity(hcn_server s, int *dd_slots, int *qd_slots);
+
+/* Queue a request; gamma host [2][P], x0 host [n][2][P] (copied). */
+int hcn_server_submit(hcn_server s, int64_t id, hcn_sys sys, const double *gamma,
+                      const double *x0, double t_arrival);
+
+/* One scheduling round; returns the number of paths in flight. */
+int hcn_server_pump(hcn_server s);
+
+/* Pop one completed request: returns 1 (and fills the outputs that are not
+ * NULL; x_out host [n][2][P]) or 0 when none is waiting. */
+int hcn_server_fetch(hcn_server s, int64_t *id, double *x_out, hcn_path_result *res,
+                     double *t_arrival, double *t_admit, double *t_done);
+int hcn_server_queued(hcn_server s, int *dd, int *qd);
 
 /* ------------------------------------------------------------------------
  * Elementwise arithmetic (the DD/QD layer itself, Section 3.1), for

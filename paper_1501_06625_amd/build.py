@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libhcn.so")
-SOURCES = ["capi.hip", "eval.hip", "mgs.hip", "track.hip", "elementwise.hip", "prof.hip", "mgs_big.hip", "mixed.hip", "tune.hip", "batch.hip"]
+SOURCES = ["capi.hip", "eval.hip", "mgs.hip", "track.hip", "elementwise.hip", "prof.hip", "mgs_big.hip", "mixed.hip", "tune.hip", "batch.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -174,6 +174,14 @@ __global__ __launch_bounds__(MGS_THREADS) void k_b_mgs(BatchDev d, const int *sl
     mgs_wg<R, GRP>(p);
 }
 
+__global__ void k_b_counts(BatchDev d, int cap, int32_t *out) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= cap) return;
+    const bool occ = d.slot_sys[s] >= 0;
+    out[2 * s] = occ ? d.st[s].evals : 0;
+    out[2 * s + 1] = occ ? d.st[s].solves : 0;
+}
+
 __global__ void k_b_flags(BatchDev d, int cap, int32_t *done, int32_t *running) {
     __shared__ int red[256 / 64];
     int c = 0;
@@ -613,6 +621,24 @@ int hcn_batch_poll(hcn_batch b, int32_t *done, void *stream) {
     if (e) return bfail(HCN_EDEVICE, "hcn_batch_poll: copy failed");
     if (done) std::memcpy(done, b->h_done, sizeof(int32_t) * b->cap);
     return *b->h_running;
+}
+
+int hcn_batch_counts(hcn_batch b, int32_t *counts, void *stream) {
+    if (!b || !counts) return bfail(HCN_EINVAL, "hcn_batch_counts: NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    int32_t *dbuf = nullptr;
+    if (hipMallocAsync((void **)&dbuf, sizeof(int32_t) * 2 * b->cap, s) != hipSuccess)
+        return bfail(HCN_ENOMEM, "hcn_batch_counts: allocation failed");
+    if (b->dirty) {
+        if (hipStreamSynchronize(s) != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_counts: sync");
+        const int rc = rebuild(b);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_b_counts, dim3((b->cap + 255) / 256), dim3(256), 0, s, b->d, b->cap, dbuf);
+    hipError_t e = hipMemcpyAsync(counts, dbuf, sizeof(int32_t) * 2 * b->cap, hipMemcpyDeviceToHost, s);
+    (void)hipFreeAsync(dbuf, s);
+    if (!e) e = hipStreamSynchronize(s);
+    return e ? bfail(HCN_EDEVICE, "hcn_batch_counts: copy failed") : HCN_OK;
 }
 
 int hcn_batch_result(hcn_batch b, int slot, double *x_out, hcn_path_result *res, void *stream) {

@@ -9,6 +9,10 @@
 //            for p = k-2..1: dS/dy_p = F_{p-1} B, B = B y_p;  dS/dy_0 = B
 // i.e. 3k-5 complex products.  Exponents above one: m = c x^a is c' S with
 // the common factor c' = c prod x_l^(a_l - 1), and dm/dx_l = a_l c' dS/dy_l.
+// The factor c' is applied once, to the start of the backward product
+// (B' = c' y_{k-1}), which carries it into every partial but the last:
+// 3k-3 complex products for the value and all partials, coefficient
+// included.
 // The value and the k partials go to consecutive slots of the monomial's
 // k-group (position-major, so a wavefront writes 64 consecutive slots).
 //
@@ -28,6 +32,15 @@ template <class R>
 HCN_DEV cx<R> load_y(const SysView &s, const double *xb, int xP, int p, int m) {
     const int v = s.pos[(size_t)p * s.nmon + m];
     return cload_s<R>(xb + (size_t)v * 2 * xP, xP);
+}
+
+// a d for the exponent a of a variable: 1 leaves d, 2 doubles every limb
+// (exact), larger exponents multiply by a double
+template <class R>
+HCN_DEV cx<R> exp_scale(const cx<R> &d, int a) {
+    if (a == 1) return d;
+    if (a == 2) return cscale2(d);
+    return cscale_d(d, (double)a);
 }
 
 template <class R>
@@ -81,23 +94,15 @@ HCN_DEV void mon_one(const SysView &s, int m, const double *xb, int xP, double *
     const cx<R> cp = has_pc ? cmul(c, pc) : c;
     if (k == 1) {
         cstore(out + (size_t)slot * W, cmul(cp, ylast));
-        if (MODE != MON_VALUES) {
-            const int a0 = s.ex[m];
-            const cx<R> d = (a0 == 1) ? cp : cscale_d(cp, (double)a0);
-            cstore(out + (size_t)(slot + stride) * W, d);
-        }
+        if (MODE != MON_VALUES) cstore(out + (size_t)(slot + stride) * W, exp_scale(cp, s.ex[m]));
         return;
     }
-    const cx<R> S = cmul(Flast, ylast);
-    cstore(out + (size_t)slot * W, cmul(cp, S));
+    // the coefficient rides on the backward product: B' = c' y_{k-1}
+    cx<R> Bk = cmul(cp, ylast);
+    cstore(out + (size_t)slot * W, cmul(Flast, Bk));
     if (MODE == MON_VALUES) return;
-    {
-        const int e = s.ex[(size_t)(k - 1) * s.nmon + m];
-        cx<R> d = cmul(cp, Flast);
-        if (e != 1) d = cscale_d(d, (double)e);
-        cstore(out + (size_t)(slot + k * stride) * W, d);
-    }
-    cx<R> Bk = ylast;
+    cstore(out + (size_t)(slot + k * stride) * W,
+           exp_scale(cmul(cp, Flast), s.ex[(size_t)(k - 1) * s.nmon + m]));
 #pragma unroll
     for (int p = KB - 2; p >= 1; --p) {
         if (p <= k - 2) {
@@ -107,19 +112,12 @@ HCN_DEV void mon_one(const SysView &s, int m, const double *xb, int xP, double *
             } else {
                 Fpm1 = cload<R>(out + (size_t)(slot + (p + 1) * stride) * W);
             }
-            const int e = s.ex[(size_t)p * s.nmon + m];
-            cx<R> d = cmul(cp, cmul(Fpm1, Bk));
-            if (e != 1) d = cscale_d(d, (double)e);
-            cstore(out + (size_t)(slot + (p + 1) * stride) * W, d);
+            cstore(out + (size_t)(slot + (p + 1) * stride) * W,
+                   exp_scale(cmul(Fpm1, Bk), s.ex[(size_t)p * s.nmon + m]));
             Bk = cmul(Bk, load_y<R>(s, xb, xP, p, m));
         }
     }
-    {
-        const int e = s.ex[m];
-        cx<R> d = cmul(cp, Bk);
-        if (e != 1) d = cscale_d(d, (double)e);
-        cstore(out + (size_t)(slot + stride) * W, d);
-    }
+    cstore(out + (size_t)(slot + stride) * W, exp_scale(Bk, s.ex[m]));
 }
 
 template <class R>

@@ -57,6 +57,8 @@ struct PathState {
     double t_acc, t_prev, dt, t;
     int32_t phase, nsucc, steps, accepted, newton_iters, end_iters, end_status,
         have_prev, status, refine_started, finalized;
+    // work counters: residual evaluations and solves since the path started
+    int32_t evals, solves;
 };
 
 enum { PHASE_TRACK = 0, PHASE_REFINE = 1, PHASE_DONE = 2 };

@@ -5,11 +5,12 @@
 // i < k; the Newton update x += dx with its norm and the Fig. 2 tests that
 // follow it).
 //
-// mgs_wg: right-looking.  For column k the first lane group forms
-// ||a_k||^2, one lane takes r_kk = sqrt, 1/r_kk, every lane scales its rows
-// of a_k, then each lane group owns trailing columns j > k (the right-hand
+// mgs_wg: right-looking.  Every lane forms r_kk = sqrt(||a_k||^2) and
+// 1/r_kk from the norm in LDS (same bits in every lane) and scales its rows
+// of a_k; then each lane group owns trailing columns j > k (the right-hand
 // side last), forms r_kj = q_k^H a_j over its rows and a butterfly across
-// its GROUP lanes, and updates a_j -= r_kj q_k on its rows.  Butterflies add
+// its GROUP lanes, and updates a_j -= r_kj q_k on its rows; the group that
+// updates column k+1 forms its norm right after (two barriers per column).  Butterflies add
 // the lower lane's value first, so every lane of a group holds bitwise the
 // same sum.  When [A | b] fits in LDS the workgroup copies it there first;
 // the arithmetic is the same either way.
@@ -75,6 +76,7 @@ HCN_DEV int fig2_decide(const MgsProblem &p) {
     const double res = residual_norm(p);
     st.res = res;
     st.c_iter += 1;
+    st.evals += 1;
     int decided = 0;
     if (res != res) {
         st.c_status = HCN_NAN;
@@ -93,6 +95,7 @@ HCN_DEV int fig2_decide(const MgsProblem &p) {
 // Fig. 2 after the update
 HCN_DEV void fig2_after_update(PathState &st, double dxn) {
     st.dxn = dxn;
+    st.solves += 1;
     if (dxn != dxn) {
         st.c_status = HCN_NAN;
         st.c_active = 0;
@@ -218,7 +221,7 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
     constexpr int NGRP = MGS_THREADS / GRP;
     extern __shared__ double lds_cols[];
     __shared__ int s_flag;
-    __shared__ double s_inv[4];
+    __shared__ double s_norm[4];
     const int tid = threadIdx.x;
     const int g = tid / GRP;
     const int lane = tid % GRP;
@@ -243,38 +246,41 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
         if (p.lds) return lds_cols + (size_t)j * cst;
         return j < n ? p.A + (size_t)j * p.A_cstride : p.bcol;
     };
+    // ||a_k||^2 over the rows of group 0, lower lane first
+    auto group0_norm2 = [&](const double *ak) -> R {
+        R s = rmake<R>(0.0);
+        bool first = true;
+        for (int i = lane; i < N; i += GRP) {
+            const R v = cnorm2(cload<R>(ak + (size_t)i * W));
+            s = first ? v : add(s, v);
+            first = false;
+        }
+        return group_sum<R, GRP>(s, lane);
+    };
     if (tid == 0) s_flag = 0;
+    __syncthreads();
+    if (g == 0) {
+        const R s0 = group0_norm2(col(0));
+        if (lane == 0) rstore(s_norm, s0);
+    }
     __syncthreads();
 
     for (int k = 0; k < n; ++k) {
         double *ak = col(k);
-        if (g == 0) {
-            R s = rmake<R>(0.0);
-            bool first = true;
-            for (int i = lane; i < N; i += GRP) {
-                const R v = cnorm2(cload<R>(ak + (size_t)i * W));
-                s = first ? v : add(s, v);
-                first = false;
-            }
-            s = group_sum<R, GRP>(s, lane);
-            if (lane == 0) {
-                const R rkk = sqrt(s);
-                const bool bad = !(lead(rkk) > 0.0) || !rfinite(rkk);
-                if (bad) {
-                    s_flag = 1;
-                } else {
-                    const R iv = div(rmake<R>(1.0), rkk);
-                    rstore(p.inv + (size_t)k * P, iv);
-                    rstore(s_inv, iv);
-                    const cx<R> rc{rkk, rmake<R>(0.0)};
-                    cstore(p.R + ((size_t)k * n + k) * W, rc);
-                }
-            }
+        // every lane forms r_kk and 1/r_kk from the shared norm (same bits)
+        R s;
+        rload(s_norm, s);
+        const R rkk = sqrt(s);
+        if (!(lead(rkk) > 0.0) || !rfinite(rkk)) {
+            s_flag = 1;
+            break;
         }
-        __syncthreads();
-        if (s_flag) break;
-        R iv;
-        rload(s_inv, iv);
+        const R iv = div(rmake<R>(1.0), rkk);
+        if (tid == 0) {
+            rstore(p.inv + (size_t)k * P, iv);
+            const cx<R> rc{rkk, rmake<R>(0.0)};
+            cstore(p.R + ((size_t)k * n + k) * W, rc);
+        }
         for (int i = tid; i < N; i += MGS_THREADS) {
             double *q = ak + (size_t)i * W;
             cstore(q, cscale(iv, cload<R>(q)));
@@ -294,6 +300,11 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
             for (int i = lane; i < N; i += GRP) {
                 double *q = aj + (size_t)i * W;
                 cstore(q, csub(cload<R>(q), cmul(r, cload<R>(ak + (size_t)i * W))));
+            }
+            // look ahead: the group of column k+1 forms its norm right away
+            if (j == k + 1 && j < n) {
+                const R sn = group0_norm2(aj);
+                if (lane == 0) rstore(s_norm, sn);
             }
         }
         __syncthreads();

@@ -415,6 +415,12 @@ template <class R> HCN_DEV cx<R> cscale(const R &s, const cx<R> &a) {
     return cx<R>{mul(s, a.re), mul(s, a.im)};
 }
 
+// 2 a, exactly: every limb doubled
+HCN_DEV double twice(double a) { return 2.0 * a; }
+HCN_DEV dd twice(const dd &a) { return dd{2.0 * a.hi, 2.0 * a.lo}; }
+HCN_DEV qd twice(const qd &a) { return qd{2.0 * a.c0, 2.0 * a.c1, 2.0 * a.c2, 2.0 * a.c3}; }
+template <class R> HCN_DEV cx<R> cscale2(const cx<R> &a) { return cx<R>{twice(a.re), twice(a.im)}; }
+
 template <class R> HCN_DEV cx<R> cscale_d(const cx<R> &a, double d) {
     return cx<R>{mul_d(a.re, d), mul_d(a.im, d)};
 }

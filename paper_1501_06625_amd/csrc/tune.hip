@@ -15,12 +15,13 @@
 #include <utility>
 
 #include "internal.hpp"
+#include "mgs_common.hpp"
 
 namespace hcn {
 namespace {
 struct Choice {
     int group = 16;
-    int lds = 1;
+    int lds = 0;
 };
 std::mutex g_mu;
 std::map<std::pair<int, int>, Choice> g_table;
@@ -91,6 +92,77 @@ int hcn_tune_load(const char *path) {
         if (hcn_tune_set(P, Nb, grp, lds) != HCN_OK) rc = HCN_EINVAL;
     std::fclose(f);
     return rc;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+// Time hcn_newton_step of `sys` at the B points x_dev ([B][n][2][P], not
+// modified) for every lane-group width and LDS staging choice, and keep the
+// fastest in the table for (P, N).  Outputs the choice and its time.
+int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_group,
+                 int *best_lds, double *best_ms, void *stream) {
+    if (!sys || !x_dev || B < 1 || reps < 1) return HCN_EINVAL;
+    hcn_sys_info_t info;
+    hcn_sys_info(sys, &info);
+    const int P = info.P, N = info.N, n = info.n;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t xbytes = (size_t)B * n * 2 * P * sizeof(double);
+    const size_t wsb = hcn_newton_ws_bytes(sys, B);
+    double *x = nullptr, *norms = nullptr;
+    int32_t *status = nullptr;
+    void *ws = nullptr;
+    hipEvent_t e0, e1;
+    if (hipMalloc((void **)&x, xbytes) != hipSuccess) return HCN_ENOMEM;
+    if (hipMalloc((void **)&norms, 2 * B * sizeof(double)) != hipSuccess ||
+        hipMalloc((void **)&status, B * sizeof(int32_t)) != hipSuccess ||
+        hipMalloc(&ws, wsb) != hipSuccess) {
+        (void)hipFree(x);
+        (void)hipFree(norms);
+        (void)hipFree(status);
+        return HCN_ENOMEM;
+    }
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    const int prev_group = tune_mgs_group(P, N), prev_lds = tune_mgs_lds(P, N);
+    int bg = prev_group, bl = prev_lds, rc = HCN_OK;
+    double bms = 1e300;
+    const bool lds_fits = mgs_lds_bytes(N, n, P) <= mgs_lds_limit();
+    for (int grp : {8, 16, 32}) {
+        for (int lds = 0; lds <= (lds_fits ? 1 : 0); ++lds) {
+            tune_set(P, N, grp, lds);
+            float ms = 0.0f;
+            for (int pass = 0; pass < 2 && rc == HCN_OK; ++pass) {  // warm-up, then timed
+                (void)hipEventRecord(e0, s);
+                for (int r = 0; r < reps && rc == HCN_OK; ++r) {
+                    (void)hipMemcpyAsync(x, x_dev, xbytes, hipMemcpyDeviceToDevice, s);
+                    rc = hcn_newton_step(sys, nullptr, 1, B, nullptr, x, norms, status, ws, wsb, s);
+                }
+                (void)hipEventRecord(e1, s);
+                if (hipEventSynchronize(e1) != hipSuccess) rc = HCN_EDEVICE;
+                (void)hipEventElapsedTime(&ms, e0, e1);
+            }
+            if (rc) break;
+            if (ms / reps < bms) {
+                bms = ms / reps;
+                bg = grp;
+                bl = lds;
+            }
+        }
+    }
+    tune_set(P, N, rc ? prev_group : bg, rc ? prev_lds : bl);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(x);
+    (void)hipFree(norms);
+    (void)hipFree(status);
+    (void)hipFree(ws);
+    if (rc) return rc;
+    if (best_group) *best_group = bg;
+    if (best_lds) *best_lds = bl;
+    if (best_ms) *best_ms = bms;
+    return HCN_OK;
 }
 
 }  // extern "C"

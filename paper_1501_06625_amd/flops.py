@@ -15,6 +15,7 @@ from __future__ import annotations
 import numpy as np
 
 REAL = {
+    1: dict(add=1, mul=1, mul_d=1, div=1, sqrt=1),
     2: dict(add=20, mul=12, mul_d=8, div=16, sqrt=12),
     4: dict(add=144, mul=130, mul_d=85, div=739, sqrt=2421),
 }
@@ -29,9 +30,10 @@ def complex_costs(P: int) -> dict:
 
 def eval_monomials(ps, P: int) -> int:
     """Reverse-mode evaluation of every monomial with its coefficient:
-    4k - 4 complex products for k >= 2 (3k - 5 for the product and its
-    gradient, k + 1 for the coefficient), powers for exponents above one,
-    and a scaling by the exponent where it is not one."""
+    3k - 3 complex products for k >= 2 (3k - 5 for the product and its
+    gradient, two more to carry the coefficient), powers for exponents above
+    one, and a scaling by exponents above two (doubling is exact and not
+    counted)."""
     c = complex_costs(P)
     total = 0
     for m in range(ps.nmon):
@@ -42,9 +44,43 @@ def eval_monomials(ps, P: int) -> int:
         es = [int(e) for e in ps.exp[a:b]]
         hi = [e for e in es if e >= 2]
         cm = sum(e - 2 for e in hi) + max(len(hi) - 1, 0) + (1 if hi else 0)
-        cm += 1 if k == 1 else 4 * k - 4
-        total += cm * c["cmul"] + sum(1 for e in es if e != 1) * c["cscale_d"]
+        cm += 1 if k == 1 else 3 * k - 3
+        total += cm * c["cmul"] + sum(1 for e in es if e > 2) * c["cscale_d"]
     return total
+
+
+def eval_values(ps, P: int) -> int:
+    """Values only (the residual of the mixed-precision step): k - 1 complex
+    products for the product, the powers, the common factor and the
+    coefficient."""
+    c = complex_costs(P)
+    total = 0
+    for m in range(ps.nmon):
+        a, b = int(ps.mon_ptr[m]), int(ps.mon_ptr[m + 1])
+        k = b - a
+        if k == 0:
+            continue
+        es = [int(e) for e in ps.exp[a:b]]
+        hi = [e for e in es if e >= 2]
+        cm = sum(e - 2 for e in hi) + max(len(hi) - 1, 0) + (1 if hi else 0)
+        cm += 1 if k == 1 else k  # (k - 1) for S, one for c' S
+        total += cm * c["cmul"]
+    return total
+
+
+def eval_sums_values(ps, P: int) -> int:
+    c = complex_costs(P)
+    return int(sum(max(int(ps.eq_ptr[i + 1] - ps.eq_ptr[i]) - 1, 0) for i in range(ps.N))) * c["cadd"]
+
+
+def mixed_step(ps, P: int) -> dict:
+    """One mixed-precision iteration: the residual in P, the Jacobian and the
+    solve in FP64, the update in P."""
+    d = dict(residual=eval_values(ps, P) + eval_sums_values(ps, P),
+             jacobian=eval_monomials(ps, 1) + eval_sums(ps, 1),
+             mgs=mgs_solve(ps.N, ps.n, 1), update=newton_update(ps.n, P))
+    d["total"] = sum(d.values())
+    return d
 
 
 def eval_sums(ps, P: int) -> int:

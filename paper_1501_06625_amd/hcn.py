@@ -64,10 +64,13 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
            "hcn_set_mgs_variant", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
-           "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load",
+           "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load", "hcn_autotune",
            "hcn_batch_create", "hcn_batch_destroy", "hcn_batch_device_bytes",
            "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_step",
-           "hcn_batch_poll", "hcn_batch_result", "hcn_batch_run",
+           "hcn_batch_poll", "hcn_batch_result", "hcn_batch_run", "hcn_batch_counts",
+           "hcn_server_create", "hcn_server_destroy", "hcn_server_last_error", "hcn_server_now",
+           "hcn_server_capacity", "hcn_server_submit", "hcn_server_pump", "hcn_server_fetch",
+           "hcn_server_queued",
            "hcn_profile_reset", "hcn_profile_query"]
 
 
@@ -106,6 +109,8 @@ def _load():
     lib.hcn_tune_get.argtypes = [ci, ci, ctypes.POINTER(ci), ctypes.POINTER(ci)]
     lib.hcn_tune_save.argtypes = [ctypes.c_char_p]
     lib.hcn_tune_load.argtypes = [ctypes.c_char_p]
+    lib.hcn_autotune.argtypes = [vp, ci, vp, ci, ctypes.POINTER(ci), ctypes.POINTER(ci),
+                                 ctypes.POINTER(cd), vp]
     lib.hcn_batch_create.argtypes = [ctypes.POINTER(vp), ci, ci, ci, ci, ci,
                                      ctypes.POINTER(_TrackParams), ci, ci]
     lib.hcn_batch_destroy.argtypes = [vp]
@@ -118,6 +123,19 @@ def _load():
     lib.hcn_batch_poll.argtypes = [vp, vp, vp]
     lib.hcn_batch_result.argtypes = [vp, ci, vp, vp, vp]
     lib.hcn_batch_run.argtypes = [vp, ci, vp]
+    lib.hcn_batch_counts.argtypes = [vp, vp, vp]
+    lib.hcn_server_create.argtypes = [ctypes.POINTER(vp), sz, cd, ci, ci, ctypes.POINTER(_TrackParams),
+                                      ctypes.POINTER(_TrackParams), ci, ci]
+    lib.hcn_server_destroy.argtypes = [vp]
+    lib.hcn_server_last_error.restype = ctypes.c_char_p
+    lib.hcn_server_now.argtypes = [vp]
+    lib.hcn_server_now.restype = cd
+    lib.hcn_server_capacity.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci)]
+    lib.hcn_server_submit.argtypes = [vp, ctypes.c_int64, vp, vp, vp, cd]
+    lib.hcn_server_pump.argtypes = [vp]
+    lib.hcn_server_fetch.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), vp, vp,
+                                     ctypes.POINTER(cd), ctypes.POINTER(cd), ctypes.POINTER(cd)]
+    lib.hcn_server_queued.argtypes = [vp, ctypes.POINTER(ci), ctypes.POINTER(ci)]
     lib.hcn_profile_query.argtypes = [ctypes.c_char_p, ctypes.POINTER(cd),
                                       ctypes.POINTER(ctypes.c_int64)]
     return lib
@@ -382,6 +400,24 @@ def tune_set(P: int, N: int, mgs_group: int, mgs_lds: int) -> None:
     _check(_lib.hcn_tune_set(P, N, mgs_group, mgs_lds))
 
 
+def autotune(sys: System, x: torch.Tensor, reps: int = 5):
+    """Time every MGS variant on a Newton step at x [B][n][2][P]; keep the
+    fastest for (P, N).  Returns (group, lds, ms per step)."""
+    xb, _ = _batched(x.contiguous(), 3)
+    g, l, ms = ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(_lib.hcn_autotune(sys.handle, xb.shape[0], _ptr(xb), reps, ctypes.byref(g),
+                             ctypes.byref(l), ctypes.byref(ms), _stream()))
+    return g.value, l.value, ms.value
+
+
+def tune_save(path: str) -> None:
+    _check(_lib.hcn_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> None:
+    _check(_lib.hcn_tune_load(path.encode()))
+
+
 def tune_get(P: int, N: int):
     g, l = ctypes.c_int(), ctypes.c_int()
     _check(_lib.hcn_tune_get(P, N, ctypes.byref(g), ctypes.byref(l)))
@@ -449,6 +485,12 @@ class Batch:
     def run(self, chunk: int = 8):
         _bcheck(_lib.hcn_batch_run(self.handle, chunk, _stream()))
 
+    def counts(self):
+        """[capacity][2] int32: residual evaluations and solves per slot."""
+        c = np.zeros((self.capacity, 2), dtype=np.int32)
+        _bcheck(_lib.hcn_batch_counts(self.handle, _np_ptr(c), _stream()))
+        return c
+
     def device_bytes(self) -> int:
         return int(_lib.hcn_batch_device_bytes(self.handle))
 
@@ -457,6 +499,78 @@ class Batch:
             _lib.hcn_batch_destroy(self.handle)
             self.handle = None
             self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _scheck(rc: int) -> int:
+    if rc < 0:
+        raise HcnError(rc, _lib.hcn_server_last_error().decode())
+    return rc
+
+
+class Server:
+    """Continuous-batching server of path-tracking requests (hcn_server_*)."""
+
+    def __init__(self, budget_bytes: int, max_n: int, max_nslots: int, qd_share: float = 0.2,
+                 steps_per_round: int = 4, serial: bool = False, **track_kw):
+        self.dd_prm = track_params(2, **track_kw)
+        self.qd_prm = track_params(4, **track_kw)
+        h = ctypes.c_void_p()
+        _scheck(_lib.hcn_server_create(ctypes.byref(h), int(budget_bytes), float(qd_share), max_n,
+                                       max_nslots, ctypes.byref(self.dd_prm),
+                                       ctypes.byref(self.qd_prm), steps_per_round,
+                                       1 if serial else 0))
+        self.handle = h
+        self._n = {}
+
+    def now(self) -> float:
+        return float(_lib.hcn_server_now(self.handle))
+
+    def capacity(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _scheck(_lib.hcn_server_capacity(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def submit(self, rid: int, sys: System, gamma, x0: np.ndarray, t_arrival: float):
+        g = np.ascontiguousarray(np.asarray(gamma, dtype=np.float64).reshape(2, sys.P))
+        x = np.ascontiguousarray(x0, dtype=np.float64)
+        self._n[int(rid)] = (sys.n, sys.P)
+        _scheck(_lib.hcn_server_submit(self.handle, int(rid), sys.handle, _np_ptr(g), _np_ptr(x),
+                                       float(t_arrival)))
+
+    def pump(self) -> int:
+        return _scheck(_lib.hcn_server_pump(self.handle))
+
+    def fetch(self):
+        """One completed request as (id, x_out, result, t_arrival, t_admit, t_done) or None."""
+        rid = ctypes.c_int64()
+        ta, tb, tc = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        # sizes are known only after the id; fetch into the largest buffer
+        x = np.zeros((4096, 2, 4))
+        res = np.zeros(1, dtype=PATH_RESULT_DTYPE)
+        got = _scheck(_lib.hcn_server_fetch(self.handle, ctypes.byref(rid), _np_ptr(x),
+                                            _np_ptr(res), ctypes.byref(ta), ctypes.byref(tb),
+                                            ctypes.byref(tc)))
+        if not got:
+            return None
+        n, P = self._n.pop(rid.value)
+        xo = x.reshape(-1)[:n * 2 * P].reshape(n, 2, P).copy()
+        return rid.value, xo, res[0], ta.value, tb.value, tc.value
+
+    def queued(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _scheck(_lib.hcn_server_queued(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def free(self):
+        if self.handle:
+            _lib.hcn_server_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -661,3 +661,51 @@ def test_batch_mixed_precision_tracking(H, P):
         assert max(abs(v) for v in fv) <= 100 * GATE[P] * scale ** 6
         ok += 1
     assert ok >= 3
+
+
+# ---------------------------------------------------------------------------
+# serving: continuous batching
+# ---------------------------------------------------------------------------
+
+def test_server_results_equal_alone(H):
+    """Requests of several systems and both precisions, admitted while others
+    run (more requests than slots), give bitwise the results of tracking each
+    path alone; a one-at-a-time server gives the same."""
+    cases = [(P, c) for P in (2, 4) for c in _batch_cases(P)]
+    systems = {}
+    for P, (ps, _, _) in cases:
+        if id(ps) not in systems:
+            systems[id(ps)] = H.System(ps)
+    alone = []
+    for P, (ps, gam, x0) in cases:
+        xo, res = H.track_paths(systems[id(ps)], gam, dev(x0[None]))
+        alone.append((host(xo)[0], res[0]))
+    maxs = max(s.info().nslots for s in systems.values())
+    for serial in (False, True):
+        # a budget for about three slots per precision: requests must queue
+        probe = H.Batch(2, 1, 8, maxs)
+        per = probe.device_bytes()
+        probe.free()
+        srv = H.Server(int(per * 3 / 0.5 * 1.5), max_n=8, max_nslots=maxs, qd_share=0.5,
+                       steps_per_round=3, serial=serial)
+        cap = srv.capacity()
+        assert cap[0] >= 1 and cap[1] >= 1
+        for rid, (P, (ps, gam, x0)) in enumerate(cases):
+            srv.submit(rid, systems[id(ps)], gam, x0, srv.now())
+        got = {}
+        for _ in range(100000):
+            srv.pump()
+            while True:
+                r = srv.fetch()
+                if r is None:
+                    break
+                got[r[0]] = r
+            if len(got) == len(cases):
+                break
+        assert len(got) == len(cases)
+        for rid in range(len(cases)):
+            _, xo, res, ta, tb, tc = got[rid]
+            assert _bitwise_equal(xo, alone[rid][0]), rid
+            assert res.tobytes() == alone[rid][1].tobytes()
+            assert ta <= tb <= tc
+        srv.free()
