@@ -30,6 +30,12 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+_T0 = time.time()
+
+
+def progress(msg: str) -> None:
+    """A progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"[bench {time.time() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
 B_DD = 10240
 B_QD = 2048
 
@@ -123,18 +129,25 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single"))
         return dict(ms_per_step=ev_ms / K, wall_s=wall, B=B, ok=ok, flops=fl, kern=kern, tuned=tuned)
 
     if "dd" in legs:
+        progress("dense n=32 DD leg")
         out["dd"] = leg(2, B_DD, steps, warmup, profile=True)
     if "qd" in legs:
+        progress("dense n=32 QD leg")
         out["qd"] = leg(4, B_QD, qd_steps, 1, profile=False)
     if "single" in legs:
         # single-path latency: one Newton step of one point, stream-ordered
+        progress("single-path leg")
         out["single"] = leg(2, 1, 200, 5, profile=False)
     if "sparse512" in legs:
+        progress("sparse n=512 leg")
         out["sparse512"] = sparse512_leg(hcn, flops, S, dev)
     if "batch64" in legs:
+        progress("64-system batch leg")
         out["batch64"] = batch_leg(hcn, flops, S, dev)
     if "serve" in legs:
+        progress("serving leg")
         out["serve"] = serve_leg(hcn, S, dev)
+    progress("done")
     return out
 
 
@@ -172,6 +185,7 @@ def serve_leg(hcn, S, dev, pool: int = 32, burst: int = 384, poisson: int = 384,
         srv = hcn.Server(int(48e9), max_n=max_n, max_nslots=max_slots, qd_share=0.2,
                          steps_per_round=8, serial=serial, max_steps=max_steps)
         t0 = srv.now()
+        last = [t0]
         nxt = 0
         got = {}
         while len(got) < len(reqs):
@@ -186,6 +200,9 @@ def serve_leg(hcn, S, dev, pool: int = 32, burst: int = 384, poisson: int = 384,
                 if r is None:
                     break
                 got[r[0]] = r
+            if srv.now() - last[0] > 5.0:
+                last[0] = srv.now()
+                progress(f"serving: {len(got)}/{len(reqs)} done, {nxt} submitted")
         wall = srv.now() - t0
         cap = srv.capacity()
         srv.free()
@@ -196,13 +213,17 @@ def serve_leg(hcn, S, dev, pool: int = 32, burst: int = 384, poisson: int = 384,
                 "p99_ms": 1e3 * float(np.percentile(lat, 99)),
                 "succeeded": ok, "slots": {"dd": cap[0], "qd": cap[1]}}
 
+    progress("serving: systems loaded")
     reqs = make_requests(burst)
+    progress("serving: burst")
     cap = run(reqs, np.zeros(burst))
     lam = 0.8 * cap["paths_per_s"]
     reqs2 = make_requests(poisson)
     arr = np.cumsum(rng.exponential(1.0 / lam, size=poisson))
+    progress(f"serving: Poisson arrivals at {lam:.1f}/s")
     lat = run(reqs2, arr)
     lat["rate_per_s"] = lam
+    progress("serving: one at a time")
     sample = reqs2[:serial_sample]
     base = run(sample, np.zeros(len(sample)), serial=True)
     for s in loaded.values():
@@ -236,7 +257,9 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
     fl_plain = [flops.newton_step(ps, 2) for ps in systems]
     fl_mixed = [flops.mixed_step(ps, 2) for ps in systems]
     res = {"systems": nsys, "paths": nsys * per, "timed_steps": steps}
+    progress("batch: systems and start points ready")
     for mode in ("plain", "mixed"):
+        progress(f"batch: {mode}")
         bt = hcn.Batch(2, nsys * per, max_n, max_slots, max_systems=nsys, mixed=(mode == "mixed"))
         for s in range(nsys):
             for q in range(per):
@@ -338,6 +361,7 @@ def main() -> int:
     cpu = None
     if rank == 0 and not args.no_cpu:
         # before the GPU is touched
+        progress("CPU oracle baseline")
         cpu = cpu_baseline()
     legs = tuple(args.legs.split(","))
     if "dd" not in legs:
