@@ -36,6 +36,8 @@ _T0 = time.time()
 def progress(msg: str) -> None:
     """A progress line on stderr (the JSON result alone goes to stdout)."""
     print(f"[bench {time.time() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
+
+
 B_DD = 10240
 B_QD = 2048
 
@@ -313,9 +315,11 @@ def sparse512_leg(hcn, flops, S, dev, reps: int = 10) -> dict:
     ws = hcn.newton_ws(sysd, 1)
     mgs_flops = flops.mgs_solve(ps.N, ps.n, 2)
     res = {}
-    names = {1: "workgroup", 2: "right_looking", 3: "column_resident"}
-    for v in (1, 2, 3):
+    runs = [(1, 16, "workgroup"), (2, 16, "right_looking"), (3, 16, "column_resident"),
+            (4, 16, "tiled_T16"), (4, 8, "tiled_T8"), (4, 4, "tiled_T4")]
+    for v, T, name in runs:
         hcn.set_mgs_variant(v)
+        hcn.set_mgs_panel(T)
         x.copy_(x0)
         hcn.newton_step(sysd, x, ws=ws)
         torch.cuda.synchronize()
@@ -334,9 +338,10 @@ def sparse512_leg(hcn, flops, S, dev, reps: int = 10) -> dict:
         hcn.profile_reset()
         step_ms = start.elapsed_time(stop) / reps
         mgs_ms = ms_mgs / max(cnt, 1)
-        res[names[v]] = {"newton_step_ms": step_ms, "mgs_ms": mgs_ms,
-                         "mgs_tflops": mgs_flops / (mgs_ms / 1e3) / 1e12}
+        res[name] = {"newton_step_ms": step_ms, "mgs_ms": mgs_ms,
+                     "mgs_tflops": mgs_flops / (mgs_ms / 1e3) / 1e12}
     hcn.set_mgs_variant(0)
+    hcn.set_mgs_panel(16)
     sysd.free()
     res["mgs_gflop"] = mgs_flops / 1e9
     return res

@@ -140,10 +140,18 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A_dev, double *b_dev,
  * 2 right-looking across workgroups (one launch per column step, the
  * trailing matrix re-read every step), 3 column-resident across workgroups
  * (one cooperative launch per problem; each workgroup keeps its columns in
- * LDS).  Variants 2 and 3 give bitwise identical results; 1 differs from
- * them only by the rounding of its reductions.  3 falls back to 2 when the
- * columns do not fit in LDS. */
+ * LDS), 4 tiled (Section 1: right-looking over panels of T columns, each
+ * panel factored by one workgroup with its columns in registers, then one
+ * launch applies the panel to every later column, held in registers:
+ * 2 ceil(n/T) launches).  Variants 2 and 3 give bitwise identical results;
+ * 1 and 4 differ from them only by the rounding of their reductions.
+ * 3 falls back to 2 when the columns do not fit in LDS, 4 falls back to 2
+ * when N > 512 (DD, FP64) or N > 256 (QD).  EINVAL outside 0..4. */
 int hcn_set_mgs_variant(int variant);
+
+/* Panel width T of variant 4 (process-wide), 1 <= T <= 16; default 16.
+ * EINVAL outside that range. */
+int hcn_set_mgs_panel(int T);
 
 /* Kernel-variant table used by the one-workgroup MGS: lane-group width
  * (8, 16 or 32 lanes per column) and LDS staging (0/1) per precision P

@@ -74,7 +74,7 @@ struct Workspace {
     }
 };
 
-int g_mgs_variant = 0;  // 0 auto, 1 workgroup per problem, 2 right-looking, 3 column-resident
+int g_mgs_variant = 0;  // 0 auto, 1 workgroup per problem, 2 right-looking, 3 column-resident, 4 tiled
 
 // choose and launch the MGS variant for B problems of size N x n
 int enqueue_mgs(int P, const MgsArgs &a, int *ints, hipStream_t s) {
@@ -824,8 +824,14 @@ int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B, const
 }
 
 int hcn_set_mgs_variant(int variant) {
-    if (variant < 0 || variant > 3) return fail(HCN_EINVAL, "hcn_set_mgs_variant: 0..3");
+    if (variant < 0 || variant > 4) return fail(HCN_EINVAL, "hcn_set_mgs_variant: 0..4");
     g_mgs_variant = variant;
+    return HCN_OK;
+}
+
+int hcn_set_mgs_panel(int T) {
+    if (T < 1 || T > 16) return fail(HCN_EINVAL, "hcn_set_mgs_panel: 1..16");
+    set_mgs_panel_width(T);
     return HCN_OK;
 }
 

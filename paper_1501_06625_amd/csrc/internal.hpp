@@ -134,6 +134,9 @@ int launch_mgs(int RP, const MgsArgs &a, hipStream_t stream);
 // holds 2B+1 ints of workspace
 int launch_mgs_big(int P, const MgsArgs &a, int variant, int *ints_dev, hipStream_t stream);
 size_t mgs_res_lds(int N, int n, int P);
+int mgs_tiled_rpl(int N, int P);
+int mgs_panel_width();
+void set_mgs_panel_width(int T);
 // the device tables of a loaded system (capi.hip)
 SysView sys_view(hcn_sys s);
 

@@ -63,7 +63,7 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_sys_degrees", "hcn_eval_ws_bytes", "hcn_eval_jac", "hcn_mgs_ws_bytes",
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
-           "hcn_set_mgs_variant", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
+           "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
            "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load", "hcn_autotune",
            "hcn_batch_create", "hcn_batch_destroy", "hcn_batch_device_bytes",
            "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_step",
@@ -102,6 +102,7 @@ def _load():
     lib.hcn_elementwise.argtypes = [ci, ci, ci, vp, vp, vp, vp]
     lib.hcn_profile_enable.argtypes = [ci]
     lib.hcn_set_mgs_variant.argtypes = [ci]
+    lib.hcn_set_mgs_panel.argtypes = [ci]
     lib.hcn_newton_mixed_ws_bytes.argtypes = [vp, ci]
     lib.hcn_newton_mixed_ws_bytes.restype = sz
     lib.hcn_newton_mixed.argtypes = lib.hcn_newton.argtypes
@@ -387,12 +388,17 @@ def profile_query(kernel: str):
     return ms.value, cnt.value
 
 
-MGS_AUTO, MGS_WORKGROUP, MGS_RIGHT_LOOKING, MGS_COLUMN_RESIDENT = 0, 1, 2, 3
+MGS_AUTO, MGS_WORKGROUP, MGS_RIGHT_LOOKING, MGS_COLUMN_RESIDENT, MGS_TILED = 0, 1, 2, 3, 4
 
 
 def set_mgs_variant(variant: int) -> None:
     """Process-wide MGS variant (see hcn_set_mgs_variant)."""
     _check(_lib.hcn_set_mgs_variant(int(variant)))
+
+
+def set_mgs_panel(T: int) -> None:
+    """Panel width of the tiled MGS variant (see hcn_set_mgs_panel)."""
+    _check(_lib.hcn_set_mgs_panel(int(T)))
 
 
 def tune_set(P: int, N: int, mgs_group: int, mgs_lds: int) -> None:

@@ -45,6 +45,9 @@ def test_host_side_argument_errors():
     assert lib.hcn_mgs_solve(1, 2, 3, 2, None, None, None, None, None, None, 0, None) == hcn.EINVAL
     assert lib.hcn_elementwise(99, 2, 1, None, None, None, None) == hcn.EINVAL
     assert lib.hcn_version() == 100
+    assert lib.hcn_set_mgs_variant(5) == hcn.EINVAL
+    assert lib.hcn_set_mgs_panel(0) == hcn.EINVAL
+    assert lib.hcn_set_mgs_panel(17) == hcn.EINVAL
     # a repeated variable inside a monomial is rejected
     eq_ptr = np.array([0, 1], dtype=np.int32)
     mon_ptr = np.array([0, 2], dtype=np.int32)

@@ -412,12 +412,57 @@ def test_mgs_big_variants_bitwise(H, P, N, n):
     assert np.abs(limb_diff(d1, d2)).max() <= tol * np.abs(lead_complex(d2)).max()
 
 
+@pytest.mark.parametrize("P,N,n,T", [(2, 300, 257, 3), (4, 200, 200, 8), (4, 256, 100, 16),
+                                     (2, 64, 64, 16), (2, 65, 1, 1), (4, 40, 33, 5), (2, 129, 96, 7)])
+def test_mgs_tiled_vs_oracle(H, P, N, n, T):
+    """Tiled variant (panel width T: ragged last panel, rows not a multiple
+    of 64, QD panels capped at eight columns) on two problems at once,
+    against the oracle's MGS."""
+    rng = np.random.default_rng(N * 3 + n + T + P)
+    A = np.stack([_rand_matrix(rng, N, n, P) for _ in range(2)])
+    b = random_points(rng, 2, N, P)
+    H.set_mgs_panel(T)
+    try:
+        dx, R, st = _solve_variant(H, H.MGS_TILED, A, b)
+    finally:
+        H.set_mgs_panel(16)
+    assert np.all(st == 0)
+    for q in range(2):
+        rc, dxo, _, Ro, _ = O.mgs_solve(P, A[q], b[q])
+        assert rc == 0
+        kappa = np.linalg.cond(lead_complex(A[q]).T)
+        tol = max(GATE[P], 16 * n * kappa * UNIT[P])
+        assert np.abs(limb_diff(dx[q], dxo)).max() <= tol * np.abs(lead_complex(dxo)).max()
+        assert np.abs(limb_diff(R[q], Ro)).max() <= tol * np.abs(lead_complex(Ro)).max()
+
+
+@pytest.mark.parametrize("T", [16, 8])
+def test_mgs_tiled_512_vs_right_looking(H, T):
+    """The full n = 512 size: tiled against right-looking (which the
+    variants test ties to the other two), within the solve tolerance."""
+    P, N, n = 2, 512, 512
+    rng = np.random.default_rng(512 + T)
+    A = _rand_matrix(rng, N, n, P)[None]
+    b = random_points(rng, 1, N, P)
+    d2, R2, s2 = _solve_variant(H, 2, A, b)
+    H.set_mgs_panel(T)
+    try:
+        d4, R4, s4 = _solve_variant(H, H.MGS_TILED, A, b)
+    finally:
+        H.set_mgs_panel(16)
+    assert s2[0] == 0 and s4[0] == 0
+    kappa = np.linalg.cond(lead_complex(A[0]).T)
+    tol = max(GATE[P], 16 * n * kappa * UNIT[P])
+    assert np.abs(limb_diff(d4, d2)).max() <= tol * np.abs(lead_complex(d2)).max()
+    assert np.abs(limb_diff(R4, R2)).max() <= tol * np.abs(lead_complex(R2)).max()
+
+
 def test_mgs_big_backward_error(H):
     P, n = 2, 160
     rng = np.random.default_rng(160)
     A = _rand_matrix(rng, n, n, P)[None]
     b = random_points(rng, 1, n, P)
-    for v in (2, 3):
+    for v in (2, 3, 4):
         d, _, s = _solve_variant(H, v, A, b)
         assert s[0] == 0
         assert _backward_error(A[0], b[0], d[0]) <= GATE[P]
@@ -429,7 +474,7 @@ def test_mgs_big_singular(H):
     A = _rand_matrix(rng, 200, 200, P)[None]
     A[0, 150] = 0.0
     b = random_points(rng, 1, 200, P)
-    for v in (2, 3):
+    for v in (2, 3, 4):
         _, _, s = _solve_variant(H, v, A, b)
         assert s[0] == H.ESINGULAR
 
@@ -442,7 +487,7 @@ def test_newton_step_sparse512_vs_oracle(H):
     x = random_points(np.random.default_rng(12), 1, ps.n, P)
     sysd = H.System(ps)
     out = {}
-    for v in (1, 3):
+    for v in (1, 3, 4):
         H.set_mgs_variant(v)
         xd = dev(x)
         norms, status = H.newton_step(sysd, xd)
@@ -454,7 +499,7 @@ def test_newton_step_sparse512_vs_oracle(H):
     f, J = O.eval_jac(ps, x[0])
     kappa = np.linalg.cond(lead_complex(J).T)
     tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
-    for v in (1, 3):
+    for v in (1, 3, 4):
         assert np.abs(limb_diff(out[v], xo)).max() <= tol * no[1], v
 
 
