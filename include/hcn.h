@@ -153,20 +153,34 @@ int hcn_set_mgs_variant(int variant);
  * EINVAL outside that range. */
 int hcn_set_mgs_panel(int T);
 
+/* Point chunking (process-wide) of hcn_newton_step, hcn_newton,
+ * hcn_newton_mixed and hcn_track_paths: each Newton iteration runs its
+ * evaluation, summation and solve launches over chunks of points whose
+ * monomial scratch, [J | -h] and R take about `bytes` (a multiple of 64
+ * points, at least 64), so that what one launch writes is still in the
+ * last-level cache when the next reads it.  0 (the default) runs every launch
+ * over the whole batch.  Results are bitwise the same for every setting. */
+int hcn_set_chunk_bytes(size_t bytes);
+
 /* Kernel-variant table used by the one-workgroup MGS: lane-group width
- * (8, 16 or 32 lanes per column) and LDS staging (0/1) per precision P
- * (1 = the FP64 solve of the mixed-precision step, 2, 4) and row count N
- * (bucketed to the next power of two >= 8).  Defaults: 16, LDS off.  The
- * choice depends only on (P, N), so a problem's result does not depend on
- * the batch it is solved in.  save/load: text, one "P N group lds" line per
- * entry.  hcn_autotune (batch section) fills the table by timing. */
+ * (8, 16 or 32 lanes per column) and the storage of [A | b] during the
+ * factorisation, mgs_lds: 0 global memory, 1 staged in LDS (when it fits in
+ * 80 KB), 2 held in the registers of the lane groups that own the columns
+ * (when N <= group * 4 and the columns fit; the slot-table batch treats 2 as
+ * 0), per precision P (1 = the FP64 solve of the mixed-precision step, 2, 4)
+ * and row count N (bucketed to the next power of two >= 8).  Defaults: 16,
+ * global memory.  Every choice gives bitwise the same results, and it depends
+ * only on (P, N), so a problem's result does not depend on the batch it is
+ * solved in.  save/load: text, one "P N group lds" line per entry.
+ * hcn_autotune (batch section) fills the table by timing.  EINVAL for a
+ * group other than 8/16/32 or mgs_lds outside 0..2. */
 int hcn_tune_set(int P, int N, int mgs_group, int mgs_lds);
 int hcn_tune_get(int P, int N, int *mgs_group, int *mgs_lds);
 int hcn_tune_save(const char *path);
 int hcn_tune_load(const char *path);
 
 /* Autotuner: times hcn_newton_step of `sys` at the B points x_dev (device
- * [B][n][2][P], left unchanged) for every lane-group width and LDS choice
+ * [B][n][2][P], left unchanged) for every lane-group width and storage choice
  * (reps steps each after a warm-up pass, HIP events on `stream`), stores the
  * fastest in the table for (P, N) and returns it.  Synchronous. */
 int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_group,
@@ -298,6 +312,17 @@ int hcn_batch_add(hcn_batch b, int slot, hcn_sys sys, const double *gamma,
 /* Free a slot (its result is no longer available). */
 int hcn_batch_release(hcn_batch b, int slot);
 
+/* Slots whose system has at least min_n unknowns (0, the default: none)
+ * solve with the tiled MGS (hcn_set_mgs_variant 4; panels of 16 columns,
+ * 8 for DD/FP64 with N > 256 and QD with N > 64), launched across all such
+ * slots, instead of one workgroup per slot: lower latency per step for
+ * large systems.  Systems too large for the tiled kernels (N > 512, QD
+ * N > 256) keep the one-workgroup solve.  The choice depends only on a
+ * slot's own system, so its results stay the same alone and in any mix; it
+ * changes the rounding of the reductions against the one-workgroup solve.
+ * Takes effect at the next step.  EINVAL for a NULL batch or min_n < 0. */
+int hcn_batch_set_split(hcn_batch b, int min_n);
+
 /* Enqueue `steps` predictor-corrector steps of every unfinished path. */
 int hcn_batch_step(hcn_batch b, int steps, void *stream);
 
@@ -320,16 +345,21 @@ int hcn_batch_run(hcn_batch b, int chunk, void *stream);
 
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of path-tracking requests of many systems
- * and two precisions.  One slot-table batch per precision; its slot count
- * is its share of budget_bytes (qd_share for QD) divided by the device
- * footprint of one slot sized for systems with N == n <= max_n and at most
- * max_nslots evaluation slots, so requests are admitted by device-memory
- * footprint: a request waits in its precision's FIFO queue until a slot is
- * free.  hcn_server_pump harvests finished paths, admits queued requests
- * and advances every path by steps_per_round steps; requests admitted
- * while others run join the same launches, and a result does not depend on
- * the mix.  serial != 0 runs one path at a time (a baseline).  Times are
- * seconds on the server's monotonic clock (hcn_server_now).
+ * and two precisions.  One slot-table batch (a lane, on its own stream) per
+ * precision and size class of the system (n <= 24, 25..63, >= 64); a lane's
+ * slot count is its share of budget_bytes (qd_share for QD, split evenly
+ * over the classes) divided by the device footprint of one slot sized for
+ * the largest system of its class (N == n <= max_n, at most max_nslots
+ * evaluation slots), so requests are admitted by device-memory footprint:
+ * a request waits in its lane's FIFO queue until a slot is free.
+ * hcn_server_pump visits every lane whose last round has finished on the
+ * device (it never waits for a busy one): it harvests finished paths,
+ * admits queued requests and launches the lane's next round of
+ * steps_per_round steps.  Requests admitted while others run join the same
+ * launches, and a result does not depend on the mix; systems with n >= 48
+ * solve with the tiled MGS across workgroups (hcn_batch_set_split).
+ * serial != 0 runs one path at a time, oldest request first (a baseline).
+ * Times are seconds on the server's monotonic clock (hcn_server_now).
  * --------------------------------------------------------------------- */
 
 typedef struct hcn_server_s *hcn_server;
@@ -346,7 +376,8 @@ int hcn_server_capacity(hcn_server s, int *dd_slots, int *qd_slots);
 int hcn_server_submit(hcn_server s, int64_t id, hcn_sys sys, const double *gamma,
                       const double *x0, double t_arrival);
 
-/* One scheduling round; returns the number of paths in flight. */
+/* One scheduling pass (no wait on busy lanes); returns the number of paths
+ * in flight, or a negative error code. */
 int hcn_server_pump(hcn_server s);
 
 /* Pop one completed request: returns 1 (and fills the outputs that are not

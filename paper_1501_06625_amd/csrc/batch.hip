@@ -5,7 +5,10 @@
 // Per step: begin (one workgroup per slot: trial t, predictor), then
 // max_iter times { monomials (one workgroup per (slot, block of 256
 // monomials)), sums (one per (slot, block of 256 outputs)), MGS (one per
-// slot, one launch per lane-group width) }, then end (controller).  The
+// slot, one launch per lane-group width; or, for slots whose system has at
+// least split_n unknowns, the tiled MGS of mgs_tiled.hpp: a panel launch and
+// a trailing launch per panel of columns, each covering all such slots) },
+// then end (controller).  The
 // work lists are rebuilt on the host when slots are added or released; the
 // step is captured once into a HIP graph and replayed.  Each slot's
 // arithmetic depends only on its own system, point and tuning entry, so a
@@ -20,6 +23,7 @@
 #include "eval_body.hpp"
 #include "internal.hpp"
 #include "mgs_common.hpp"
+#include "mgs_tiled.hpp"
 #include "mp.hpp"
 #include "prof.hpp"
 #include "track_body.hpp"
@@ -35,6 +39,7 @@ struct BatchDev {
     double *x, *x_acc, *x_prev, *x_out, *sc, *J, *R, *inv, *dx, *np, *t, *gamma;
     PathState *st;
     hcn_path_result *res;
+    int *sing;            // [cap] singular column seen by the tiled MGS
     long xs, scs, Js, Rs, invs, nps;
     TrackArgs prm;
 };
@@ -149,10 +154,10 @@ __global__ __launch_bounds__(MGS_THREADS) void k_b_mixed_update(BatchDev d, cons
     if (threadIdx.x == 0) fig2_after_update(st, dxn);
 }
 
-template <class R, int GRP>
-__global__ __launch_bounds__(MGS_THREADS) void k_b_mgs(BatchDev d, const int *slots) {
+// the solve of one slot with every pointer resolved (R: solve precision)
+template <class R>
+HCN_DEV MgsProblem slot_problem(const BatchDev &d, int slot) {
     constexpr int W = 2 * limbs<R>::P;
-    const int slot = slots[blockIdx.x];
     const SysView &s = d.sys[d.slot_sys[slot]];
     MgsProblem p;
     p.N = s.N;
@@ -171,7 +176,52 @@ __global__ __launch_bounds__(MGS_THREADS) void k_b_mgs(BatchDev d, const int *sl
     p.nparts = (int)(((long)s.n * s.N + s.N + 255) / 256);
     p.norms = nullptr;
     p.st = d.st + slot;
-    mgs_wg<R, GRP>(p);
+    return p;
+}
+
+template <class R, int GRP>
+__global__ __launch_bounds__(MGS_THREADS) void k_b_mgs(BatchDev d, const int *slots) {
+    mgs_wg<R, GRP>(slot_problem<R>(d, slots[blockIdx.x]));
+}
+
+// tiled MGS of the large slots: the Fig. 2 tests before the solve (already
+// taken by the residual pass in mixed mode) and a cleared singular flag
+__global__ void k_bt_pre(BatchDev d, const int *slots, int count) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= count) return;
+    const int slot = slots[q];
+    d.sing[slot] = 0;
+    if (!d.mixed) (void)fig2_decide(slot_problem<double>(d, slot));
+}
+
+template <class R, int RPL>
+__global__ __launch_bounds__((64 * tiled_max_waves<R, RPL>())) void k_bt_panel(BatchDev d, const int *slots,
+                                                                                 int k0, int T) {
+    extern __shared__ double qbuf[];
+    const int slot = slots[blockIdx.x];
+    if (!d.st[slot].c_active || d.sing[slot]) return;
+    const MgsProblem p = slot_problem<R>(d, slot);
+    if (k0 >= p.n) return;
+    tiled_panel<R, RPL>(p, k0, min(k0 + T, p.n), d.sing + slot, qbuf);
+}
+
+template <class R, int RPL>
+__global__ __launch_bounds__(MGS_THREADS) void k_bt_trail(BatchDev d, const int *slots, int k0, int T) {
+    const int slot = slots[blockIdx.y];
+    if (!d.st[slot].c_active || d.sing[slot]) return;
+    const MgsProblem p = slot_problem<R>(d, slot);
+    if (k0 >= p.n) return;
+    const int k1 = min(k0 + T, p.n);
+    const int j = k1 + 4 * (int)blockIdx.x + (int)(threadIdx.x >> 6);
+    if (j > p.n) return;
+    tiled_trail<R, RPL>(p, k0, k1, j);
+}
+
+template <class R>
+__global__ __launch_bounds__(MGS_THREADS) void k_bt_finish(BatchDev d, const int *slots) {
+    const int slot = slots[blockIdx.x];
+    if (!d.st[slot].c_active) return;
+    mgs_epilogue<R>(slot_problem<R>(d, slot), d.sing[slot] != 0);
 }
 
 __global__ void k_b_counts(BatchDev d, int cap, int32_t *out) {
@@ -243,6 +293,10 @@ struct hcn_batch_s {
     int2 *d_mon = nullptr, *d_sum = nullptr, *d_sumf = nullptr;
     int *d_slots = nullptr;
     int n_mon = 0, n_sum = 0, n_sumf = 0, n_slots = 0;
+    // large slots (n >= split_n; 0: none) solve with the tiled MGS
+    int split_n = 0;
+    int *d_big = nullptr;
+    int n_big = 0, big_maxn = 0, big_maxN = 0;
     int grp_off[3] = {0, 0, 0}, grp_cnt[3] = {0, 0, 0};
     size_t grp_lds[3] = {0, 0, 0};
     long mon_cap = 0, sum_cap = 0;
@@ -273,8 +327,37 @@ void launch_b_mon(hcn_batch_s *b, hipStream_t s) {
     }
 }
 
+template <class R, int RPL>
+void launch_b_tiled_rpl(hcn_batch_s *b, hipStream_t s) {
+    const BatchDev &d = b->d;
+    constexpr int T = tiled_max_waves<R, RPL>();
+    const size_t lds = (size_t)b->big_maxN * 2 * limbs<R>::P * sizeof(double);
+    for (int k0 = 0; k0 < b->big_maxn; k0 += T) {
+        hipLaunchKernelGGL((k_bt_panel<R, RPL>), dim3(b->n_big), dim3(64 * T), lds, s, d, b->d_big, k0, T);
+        const int cols = b->big_maxn + 1 - std::min(k0 + T, b->big_maxn);
+        hipLaunchKernelGGL((k_bt_trail<R, RPL>), dim3((cols + 3) / 4, b->n_big), dim3(MGS_THREADS), 0, s, d,
+                           b->d_big, k0, T);
+    }
+}
+
+template <class R>
+void launch_b_tiled(hcn_batch_s *b, hipStream_t s) {
+    if (b->n_big == 0) return;
+    hipLaunchKernelGGL(k_bt_pre, dim3((b->n_big + 255) / 256), dim3(256), 0, s, b->d, b->d_big, b->n_big);
+    switch (tiled_rpl(b->big_maxN, limbs<R>::P)) {
+        case 1: launch_b_tiled_rpl<R, 1>(b, s); break;
+        case 2: launch_b_tiled_rpl<R, 2>(b, s); break;
+        case 4: launch_b_tiled_rpl<R, 4>(b, s); break;
+        default:
+            if constexpr (limbs<R>::P != 4) launch_b_tiled_rpl<R, 8>(b, s);
+            break;
+    }
+    hipLaunchKernelGGL(k_bt_finish<R>, dim3(b->n_big), dim3(MGS_THREADS), 0, s, b->d, b->d_big);
+}
+
 template <class R>
 void launch_b_mgs(hcn_batch_s *b, hipStream_t s) {
+    launch_b_tiled<R>(b, s);
     const BatchDev &d = b->d;
     const int grps[3] = {8, 16, 32};
     for (int g = 0; g < 3; ++g) {
@@ -325,11 +408,20 @@ void set_lds_attributes() {
     (void)hipFuncSetAttribute((const void *)k_b_mgs<R, 32>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
 }
 
+// a slot solves with the tiled MGS when its system has at least split_n
+// unknowns and its columns fit the tiled kernels' registers; this depends
+// on the slot's own system only, so a path's bits do not depend on the mix
+bool big_slot(const hcn_batch_s *b, const SysView &v) {
+    const int Ps = b->d.mixed ? 1 : b->P;
+    return b->split_n > 0 && v.n >= b->split_n && tiled_rpl(v.N, Ps) > 0;
+}
+
 // work lists from the occupied slots; slots grouped by MGS lane-group width
 int rebuild(hcn_batch_s *b) {
     std::vector<int2> mon, sum, sumf;
-    std::vector<int> lists[3];
+    std::vector<int> lists[3], big;
     const int Ps = b->d.mixed ? 1 : b->P;  // precision of the solve
+    b->big_maxn = b->big_maxN = 0;
     const int grps[3] = {8, 16, 32};
     size_t lds_need[3] = {0, 0, 0};
     for (int s = 0; s < b->cap; ++s) {
@@ -341,11 +433,18 @@ int rebuild(hcn_batch_s *b) {
         for (int q = 0; q < sb; ++q) sum.push_back(make_int2(s, q));
         const int sf = sum_nparts(v, 0);
         for (int q = 0; q < sf; ++q) sumf.push_back(make_int2(s, q));
+        b->slot_lds[s] = 0;
+        if (big_slot(b, v)) {
+            big.push_back(s);
+            b->big_maxn = std::max(b->big_maxn, v.n);
+            b->big_maxN = std::max(b->big_maxN, v.N);
+            continue;
+        }
         const int grp = tune_mgs_group(Ps, v.N);
         const int g = grp == 8 ? 0 : grp == 32 ? 2 : 1;
         lists[g].push_back(s);
         const size_t bytes = mgs_lds_bytes(v.N, v.n, Ps);
-        const int lds = (bytes <= mgs_lds_limit() && tune_mgs_lds(Ps, v.N)) ? 1 : 0;
+        const int lds = (bytes <= mgs_lds_limit() && tune_mgs_lds(Ps, v.N) == 1) ? 1 : 0;
         b->slot_lds[s] = lds;
         if (lds) lds_need[g] = std::max(lds_need[g], bytes);
         (void)grps;
@@ -360,6 +459,11 @@ int rebuild(hcn_batch_s *b) {
     b->n_mon = (int)mon.size();
     b->n_sum = (int)sum.size();
     b->n_sumf = (int)sumf.size();
+    // the large slots follow the others in the slot list: begin, end and the
+    // mixed-precision kernels cover all, the one-workgroup MGS its groups only
+    b->n_big = (int)big.size();
+    slots.insert(slots.end(), big.begin(), big.end());
+    b->d_big = b->d_slots + (slots.size() - big.size());
     b->n_slots = (int)slots.size();
     if ((long)mon.size() > b->mon_cap || (long)sum.size() > b->sum_cap)
         return bfail(HCN_EINVAL, "hcn_batch: work list exceeds its capacity");
@@ -423,7 +527,7 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
                  o_ss = take(cap * 4), o_sl = take(cap * 4), o_mon = take(b->mon_cap * sizeof(int2)),
                  o_sum = take(b->sum_cap * sizeof(int2)), o_sumf = take(cap * ((max_n + 255) / 256) * sizeof(int2)),
                  o_slots = take(cap * 4), o_done = take(cap * 4),
-                 o_run = take(4);
+                 o_run = take(4), o_sing = take(cap * 4);
     b->bytes = off;
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
         delete b;
@@ -448,6 +552,7 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
     d.gamma = (double *)(base + o_g);
     d.st = (PathState *)(base + o_st);
     d.res = (hcn_path_result *)(base + o_res);
+    d.sing = (int *)(base + o_sing);
     d.xs = xs;
     d.scs = scs;
     d.Js = Js;
@@ -562,6 +667,13 @@ int hcn_batch_add(hcn_batch b, int slot, hcn_sys sys, const double *gamma, const
         hipLaunchKernelGGL(k_b_init<qd>, dim3(1), dim3(64), 0, s, b->d, slot, x0);
     b->dirty = true;
     return hipGetLastError() == hipSuccess ? HCN_OK : bfail(HCN_EDEVICE, "hcn_batch_add: launch failed");
+}
+
+int hcn_batch_set_split(hcn_batch b, int min_n) {
+    if (!b || min_n < 0) return bfail(HCN_EINVAL, "hcn_batch_set_split: bad argument");
+    b->split_n = min_n;
+    b->dirty = true;
+    return HCN_OK;
 }
 
 int hcn_batch_release(hcn_batch b, int slot) {

@@ -75,13 +75,71 @@ struct Workspace {
 };
 
 int g_mgs_variant = 0;  // 0 auto, 1 workgroup per problem, 2 right-looking, 3 column-resident, 4 tiled
+size_t g_chunk_bytes = 0;  // 0: every launch covers the whole batch
+
+// the MGS variant for B problems with n unknowns
+int mgs_variant_for(int n, int B) {
+    if (g_mgs_variant != 0) return g_mgs_variant;
+    return (n >= 160 && B <= 4) ? 2 : 1;
+}
+
+int enqueue_mgs_variant(int P, const MgsArgs &a, int variant, int *ints, hipStream_t s) {
+    if (variant == 1) return launch_mgs(P, a, s);
+    return launch_mgs_big(P, a, variant, ints, s);
+}
 
 // choose and launch the MGS variant for B problems of size N x n
 int enqueue_mgs(int P, const MgsArgs &a, int *ints, hipStream_t s) {
-    int v = g_mgs_variant;
-    if (v == 0) v = (a.n >= 160 && a.B <= 4) ? 2 : 1;
-    if (v == 1) return launch_mgs(P, a, s);
-    return launch_mgs_big(P, a, v, ints, s);
+    return enqueue_mgs_variant(P, a, mgs_variant_for(a.n, a.B), ints, s);
+}
+
+// Points per chunk: the monomial scratch, [J | -h] and R of one chunk take
+// about g_chunk_bytes, so that what one launch writes is still in the
+// last-level cache when the next launch reads it.  A multiple of 64, at
+// least 64, at most B.
+int chunk_points(const SysView &v, int B, int RP) {
+    if (g_chunk_bytes == 0) return B;
+    const size_t per =
+        ((size_t)v.nslots + 2 * (size_t)(v.n + 1) * v.N) * 2 * (size_t)RP * sizeof(double);
+    long c = (long)(g_chunk_bytes / std::max<size_t>(per, 1));
+    c = std::max<long>(64, c / 64 * 64);
+    return (int)std::min<long>(c, B);
+}
+
+// the same launch arguments restricted to points b0 .. b0 + Bc - 1
+MonArgs chunk_of(MonArgs m, int b0, int Bc) {
+    m.B = Bc;
+    m.x += (size_t)b0 * m.x_pstride;
+    m.scratch += (size_t)b0 * m.sc_pstride;
+    if (m.st) m.st += b0;
+    return m;
+}
+
+SumArgs chunk_of(SumArgs a, int b0, int Bc) {
+    a.B = Bc;
+    a.scratch += (size_t)b0 * a.sc_pstride;
+    a.x += (size_t)b0 * a.x_pstride;
+    if (a.hom.on) a.hom.t += b0;
+    if (a.J) a.J += (size_t)b0 * a.J_pstride;
+    if (a.f) a.f += (size_t)b0 * a.f_pstride;
+    if (a.norm_part) a.norm_part += (size_t)b0 * sum_nparts(a.s, a.jac);
+    if (a.st) a.st += b0;
+    return a;
+}
+
+MgsArgs chunk_of(MgsArgs a, int b0, int Bc) {
+    a.B = Bc;
+    a.A += (size_t)b0 * a.A_pstride;
+    if (a.bcol) a.bcol += (size_t)b0 * a.b_pstride;
+    a.R += (size_t)b0 * a.R_pstride;
+    a.inv += (size_t)b0 * a.inv_pstride;
+    a.dx += (size_t)b0 * a.dx_pstride;
+    if (a.status) a.status += b0;
+    if (a.x) a.x += (size_t)b0 * a.x_pstride;
+    if (a.norm_part) a.norm_part += (size_t)b0 * a.nparts;
+    if (a.norms) a.norms += 2 * (size_t)b0;
+    if (a.st) a.st += b0;
+    return a;
 }
 
 }  // namespace
@@ -407,9 +465,10 @@ SumArgs sum_args(const SysView &v, int B, const double *scratch, int RP, const d
 // evaluation of f (or h) and J into the augmented [J | -h] of the Newton
 // workspace, with the residual norm parts
 int enqueue_eval_aug(const SysView &v, int B, const double *x, const Homotopy &hom,
-                     const NewtonWs &w, const PathState *st, hipStream_t s) {
+                     const NewtonWs &w, const PathState *st, hipStream_t s, int b0 = 0, int Bc = -1) {
     const long W = 2 * v.P;
-    int e = launch_mon(v.P, mon_args(v, B, x, w.ev.scratch, v.P, st, 0), s);
+    if (Bc < 0) Bc = B - b0;
+    int e = launch_mon(v.P, chunk_of(mon_args(v, B, x, w.ev.scratch, v.P, st, 0), b0, Bc), s);
     if (e) return dev_fail(e, "evaluation launch");
     SumArgs a = sum_args(v, B, w.ev.scratch, v.P, x, hom, st);
     a.J = w.Jaug;
@@ -419,8 +478,25 @@ int enqueue_eval_aug(const SysView &v, int B, const double *x, const Homotopy &h
     a.f_pstride = (long)(v.n + 1) * v.N * W;
     a.f_neg = 1;
     a.norm_part = w.ev.norm_part;
-    e = launch_sum(v.P, a, s);
+    e = launch_sum(v.P, chunk_of(a, b0, Bc), s);
     if (e) return dev_fail(e, "summation launch");
+    return HCN_OK;
+}
+
+// One Newton iteration over the batch (evaluation into [J | -h], then the
+// solve), a chunk of points at a time; every point's arithmetic is the same
+// whatever the chunk.
+int enqueue_newton_iter(const SysView &v, int B, const double *x, const Homotopy &hom,
+                        const NewtonWs &w, const PathState *st, const MgsArgs &a, hipStream_t s) {
+    const int variant = mgs_variant_for(v.n, B);
+    const int C = chunk_points(v, B, v.P);
+    for (int b0 = 0; b0 < B; b0 += C) {
+        const int Bc = std::min(C, B - b0);
+        const int rc = enqueue_eval_aug(v, B, x, hom, w, st, s, b0, Bc);
+        if (rc) return rc;
+        const int e = enqueue_mgs_variant(v.P, chunk_of(a, b0, Bc), variant, w.ints, s);
+        if (e) return dev_fail(e, "solve launch");
+    }
     return HCN_OK;
 }
 
@@ -575,12 +651,10 @@ int hcn_newton_step(hcn_sys sys, const double *gamma, int relax_k, int B, const 
     if (rc) return rc;
     Carver c(wsp.ptr);
     NewtonWs w = carve_newton(c, v, B);
-    rc = enqueue_eval_aug(v, B, x, hom, w, nullptr, s);
-    if (rc) return rc;
     MgsArgs a = newton_mgs_args(v, B, w, x, MGS_NEWTON_STEP);
     a.norms = norms;
     a.status = status;
-    return dev_fail(enqueue_mgs(v.P, a, w.ints, s), "hcn_newton_step: solve launch");
+    return enqueue_newton_iter(v, B, x, hom, w, nullptr, a, s);
 }
 
 int hcn_newton(hcn_sys sys, const double *gamma, int relax_k, int B, const double *t, double *x,
@@ -606,10 +680,8 @@ int hcn_newton(hcn_sys sys, const double *gamma, int relax_k, int B, const doubl
     if (e) return dev_fail(e, "hcn_newton: init launch");
     const MgsArgs a = newton_mgs_args(v, B, w, x, MGS_NEWTON_FIG2);
     for (int it = 0; it < prm->max_iter; ++it) {
-        rc = enqueue_eval_aug(v, B, x, hom, w, w.st, s);
+        rc = enqueue_newton_iter(v, B, x, hom, w, w.st, a, s);
         if (rc) return rc;
-        e = enqueue_mgs(v.P, a, w.ints, s);
-        if (e) return dev_fail(e, "hcn_newton: solve launch");
     }
     e = launch_newton_finish(B, w.st, norms, status, iters, s);
     return dev_fail(e, "hcn_newton: finish launch");
@@ -683,12 +755,8 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B, const 
         for (int q = 0; q < chunk && rc == HCN_OK; ++q) {
             e = launch_track_begin(ta, s);
             if (e) { rc = dev_fail(e, "hcn_track_paths: begin launch"); break; }
-            for (int it = 0; it < prm->max_iter && rc == HCN_OK; ++it) {
-                rc = enqueue_eval_aug(v, B, w.x, hom, w.nw, w.nw.st, s);
-                if (rc) break;
-                e = enqueue_mgs(v.P, a, w.nw.ints, s);
-                if (e) rc = dev_fail(e, "hcn_track_paths: solve launch");
-            }
+            for (int it = 0; it < prm->max_iter && rc == HCN_OK; ++it)
+                rc = enqueue_newton_iter(v, B, w.x, hom, w.nw, w.nw.st, a, s);
             if (rc) break;
             e = launch_track_end(ta, s);
             if (e) rc = dev_fail(e, "hcn_track_paths: end launch");
@@ -790,34 +858,42 @@ int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B, const
     a.norm_part = w.np;
     a.nparts = sum_nparts(v, 0);
     a.st = w.st;
+    SumArgs sr = sum_args(v, B, w.sc_ext, v.P, x, hom, w.st);
+    sr.jac = 0;
+    sr.f = w.J64 + (size_t)v.n * colN;
+    sr.f_pstride = (long)(v.n + 1) * colN;
+    sr.f_neg = 1;
+    sr.f_lead_only = 1;
+    sr.norm_part = w.np;
+    SumArgs sj = sum_args(v, B, w.sc64, 1, x, hom, w.st);
+    sj.J = w.J64;
+    sj.J_cstride = colN;
+    sj.J_pstride = (long)(v.n + 1) * colN;
+    const MonArgs mr = mon_args(v, B, x, w.sc_ext, v.P, w.st, 1);
+    const MonArgs mj = mon_args(v, B, x, w.sc64, 1, w.st, 0);
+    const int variant = mgs_variant_for(v.n, B);
+    const int C = chunk_points(v, B, 1);
     for (int it = 0; it < prm->max_iter; ++it) {
-        // residual in extended precision; its rounding is the right-hand side
-        e = launch_mon(v.P, mon_args(v, B, x, w.sc_ext, v.P, w.st, 1), s);
-        if (e) return dev_fail(e, "hcn_newton_mixed: residual launch");
-        SumArgs sr = sum_args(v, B, w.sc_ext, v.P, x, hom, w.st);
-        sr.jac = 0;
-        sr.f = w.J64 + (size_t)v.n * colN;
-        sr.f_pstride = (long)(v.n + 1) * colN;
-        sr.f_neg = 1;
-        sr.f_lead_only = 1;
-        sr.norm_part = w.np;
-        e = launch_sum(v.P, sr, s);
-        if (e) return dev_fail(e, "hcn_newton_mixed: residual sum launch");
-        e = launch_fig2_pre(a, s);
-        if (e) return dev_fail(e, "hcn_newton_mixed: test launch");
-        // the Jacobian in FP64 at the leading limbs of x
-        e = launch_mon(1, mon_args(v, B, x, w.sc64, 1, w.st, 0), s);
-        if (e) return dev_fail(e, "hcn_newton_mixed: Jacobian launch");
-        SumArgs sj = sum_args(v, B, w.sc64, 1, x, hom, w.st);
-        sj.J = w.J64;
-        sj.J_cstride = colN;
-        sj.J_pstride = (long)(v.n + 1) * colN;
-        e = launch_sum(1, sj, s);
-        if (e) return dev_fail(e, "hcn_newton_mixed: Jacobian sum launch");
-        e = enqueue_mgs(1, a, w.ints, s);
-        if (e) return dev_fail(e, "hcn_newton_mixed: solve launch");
-        e = launch_mixed_update(v.P, a, s);
-        if (e) return dev_fail(e, "hcn_newton_mixed: update launch");
+        for (int b0 = 0; b0 < B; b0 += C) {
+            const int Bc = std::min(C, B - b0);
+            const MgsArgs ac = chunk_of(a, b0, Bc);
+            // residual in extended precision; its rounding is the right-hand side
+            e = launch_mon(v.P, chunk_of(mr, b0, Bc), s);
+            if (e) return dev_fail(e, "hcn_newton_mixed: residual launch");
+            e = launch_sum(v.P, chunk_of(sr, b0, Bc), s);
+            if (e) return dev_fail(e, "hcn_newton_mixed: residual sum launch");
+            e = launch_fig2_pre(ac, s);
+            if (e) return dev_fail(e, "hcn_newton_mixed: test launch");
+            // the Jacobian in FP64 at the leading limbs of x
+            e = launch_mon(1, chunk_of(mj, b0, Bc), s);
+            if (e) return dev_fail(e, "hcn_newton_mixed: Jacobian launch");
+            e = launch_sum(1, chunk_of(sj, b0, Bc), s);
+            if (e) return dev_fail(e, "hcn_newton_mixed: Jacobian sum launch");
+            e = enqueue_mgs_variant(1, ac, variant, w.ints, s);
+            if (e) return dev_fail(e, "hcn_newton_mixed: solve launch");
+            e = launch_mixed_update(v.P, ac, s);
+            if (e) return dev_fail(e, "hcn_newton_mixed: update launch");
+        }
     }
     e = launch_newton_finish(B, w.st, norms, status, iters, s);
     return dev_fail(e, "hcn_newton_mixed: finish launch");
@@ -826,6 +902,11 @@ int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B, const
 int hcn_set_mgs_variant(int variant) {
     if (variant < 0 || variant > 4) return fail(HCN_EINVAL, "hcn_set_mgs_variant: 0..4");
     g_mgs_variant = variant;
+    return HCN_OK;
+}
+
+int hcn_set_chunk_bytes(size_t bytes) {
+    g_chunk_bytes = bytes;
     return HCN_OK;
 }
 

@@ -1,6 +1,7 @@
 // mgs.hip -- modified Gram-Schmidt solve, one workgroup of 256 lanes per
-// problem (mgs_wg in mgs_common.hpp), with the lane-group width chosen by
-// the tuner (hcn_tune) and [A | b] staged in LDS when it fits.
+// problem (mgs_wg / mgs_reg in mgs_common.hpp), with the lane-group width
+// and the storage of [A | b] (global memory, LDS, registers) chosen by the
+// tuner (hcn_tune).
 #include "internal.hpp"
 #include "mgs_common.hpp"
 #include "mp.hpp"
@@ -15,10 +16,44 @@ __global__ __launch_bounds__(MGS_THREADS) void k_mgs(MgsArgs a, int lds) {
     mgs_wg<R, GRP>(p);
 }
 
+template <class R, int GRP, int RPL, int CPG>
+__global__ __launch_bounds__(MGS_THREADS) void k_mgs_reg(MgsArgs a) {
+    mgs_reg<R, GRP, RPL, CPG>(problem_of(a, blockIdx.x));
+}
+
+template <class R, int GRP>
+static bool launch_reg(const MgsArgs &a, hipStream_t stream) {
+    int rpl = 0, cpg = 0;
+    mgs_reg_shape(a.N, a.n, limbs<R>::P, GRP, &rpl, &cpg);
+    const dim3 grid(a.B), block(MGS_THREADS);
+    switch (rpl * 8 + cpg) {
+        case 9: hipLaunchKernelGGL((k_mgs_reg<R, GRP, 1, 1>), grid, block, 0, stream, a); return true;
+        case 17: hipLaunchKernelGGL((k_mgs_reg<R, GRP, 2, 1>), grid, block, 0, stream, a); return true;
+        case 33: hipLaunchKernelGGL((k_mgs_reg<R, GRP, 4, 1>), grid, block, 0, stream, a); return true;
+        default: break;
+    }
+    // QD columns beyond one per group spill to the stack
+    if constexpr (limbs<R>::P != 4) {
+        switch (rpl * 8 + cpg) {
+            case 10: hipLaunchKernelGGL((k_mgs_reg<R, GRP, 1, 2>), grid, block, 0, stream, a); return true;
+            case 12: hipLaunchKernelGGL((k_mgs_reg<R, GRP, 1, 4>), grid, block, 0, stream, a); return true;
+            case 18: hipLaunchKernelGGL((k_mgs_reg<R, GRP, 2, 2>), grid, block, 0, stream, a); return true;
+            case 20: hipLaunchKernelGGL((k_mgs_reg<R, GRP, 2, 4>), grid, block, 0, stream, a); return true;
+            case 34: hipLaunchKernelGGL((k_mgs_reg<R, GRP, 4, 2>), grid, block, 0, stream, a); return true;
+            default: break;
+        }
+    }
+    return false;
+}
+
 template <class R, int GRP>
 static void launch_grp(const MgsArgs &a, hipStream_t stream) {
+    // storage of [A | b]: 0 global memory, 1 LDS (when it fits), 2 registers
+    // (when they fit); all three give the same bits
+    const int mode = tune_mgs_lds(limbs<R>::P, a.N);
+    if (mode == 2 && launch_reg<R, GRP>(a, stream)) return;
     const size_t bytes = mgs_lds_bytes(a.N, a.n, limbs<R>::P);
-    const int lds = (bytes <= mgs_lds_limit() && tune_mgs_lds(limbs<R>::P, a.N)) ? 1 : 0;
+    const int lds = (bytes <= mgs_lds_limit() && mode == 1) ? 1 : 0;
     if (lds)
         (void)hipFuncSetAttribute((const void *)k_mgs<R, GRP>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

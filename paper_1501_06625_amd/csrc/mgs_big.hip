@@ -22,21 +22,19 @@
 // bounded spin) and apply the projection to their resident columns.  Each
 // column is read from and written to global memory once.
 //
-// Tiled (panel width T): the columns are taken T at a time.  A panel launch
-// factors columns k0..k0+T-1 in one workgroup of T wavefronts, each holding
-// one column in registers (lane l: rows l, l+64, ...); the wavefront of
-// column k normalises it and broadcasts q_k through LDS, the later ones
-// project it out (two barriers per column, no launch).  A trailing launch
-// then gives every later column (the right-hand side included) a wavefront
-// that applies the panel's T projections in order to its column, held in
-// registers, so a trailing column is read and written once per panel rather
-// than once per column.  Reductions are per wavefront (the same tree in both
-// launches), so this variant agrees with the other two to rounding, not
+// Tiled (panel width T; mgs_tiled.hpp): the columns are taken T at a time.
+// A panel launch factors columns k0..k0+T-1 in one workgroup of T
+// wavefronts, each holding one column in registers; a trailing launch gives
+// every later column (the right-hand side included) a wavefront that applies
+// the panel's T projections in order, so a trailing column is read and
+// written once per panel rather than once per column.  Reductions are per
+// wavefront, so this variant agrees with the other two to rounding, not
 // bitwise.
 #include <algorithm>
 
 #include "internal.hpp"
 #include "mgs_common.hpp"
+#include "mgs_tiled.hpp"
 #include "mp.hpp"
 #include "prof.hpp"
 
@@ -288,172 +286,30 @@ __global__ __launch_bounds__(BT) void k_mgs_res(MgsArgs a, ResArgs r) {
 }
 
 // ---------------------------------------------------------------------------
-// tiled: panel and trailing launches, one wavefront per column
+// tiled: panel and trailing launches over the bodies in mgs_tiled.hpp
 // ---------------------------------------------------------------------------
-template <class R>
-HCN_DEV cx<R> wave_csum(cx<R> v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const cx<R> o{bshfl(v.re, m), bshfl(v.im, m)};
-        v = (lane & m) ? cadd(o, v) : cadd(v, o);
-    }
-    return v;
-}
-
-template <class R>
-HCN_DEV R wave_rsum(R v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const R o = bshfl(v, m);
-        v = (lane & m) ? add(o, v) : add(v, o);
-    }
-    return v;
-}
-
-// rows lane, lane+64, ... of a column (zeros past N)
-template <class R, int RPL>
-HCN_DEV void wcol_load(cx<R> (&v)[RPL], const double *col, int N, int lane) {
-    constexpr int W = 2 * limbs<R>::P;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = lane + 64 * r;
-        v[r] = i < N ? cload<R>(col + (size_t)i * W) : czero<R>();
-    }
-}
-
-template <class R, int RPL>
-HCN_DEV void wcol_store(const cx<R> (&v)[RPL], double *col, int N, int lane) {
-    constexpr int W = 2 * limbs<R>::P;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = lane + 64 * r;
-        if (i < N) cstore(col + (size_t)i * W, v[r]);
-    }
-}
-
-// q^H v over this wavefront's column (rows in ascending order per lane)
-template <class R, int RPL>
-HCN_DEV cx<R> wcol_dot(const double *q, const cx<R> (&v)[RPL], int N, int lane) {
-    constexpr int W = 2 * limbs<R>::P;
-    cx<R> acc = czero<R>();
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = lane + 64 * r;
-        if (i < N) {
-            const cx<R> t = cmul_conj(cload<R>(q + (size_t)i * W), v[r]);
-            acc = r == 0 ? t : cadd(acc, t);
-        }
-    }
-    return wave_csum(acc);
-}
-
-template <class R, int RPL>
-HCN_DEV void wcol_axpy(const double *q, cx<R> (&v)[RPL], const cx<R> &rv, int N, int lane) {
-    constexpr int W = 2 * limbs<R>::P;
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-        const int i = lane + 64 * r;
-        if (i < N) v[r] = csub(v[r], cmul(rv, cload<R>(q + (size_t)i * W)));
-    }
-}
-
-// wavefronts (columns) per panel: 16, or 8 where a column and the
-// temporaries of its arithmetic would not fit the register budget of 1024
-// lanes (DD beyond four rows per lane, QD beyond one)
-template <class R, int RPL>
-constexpr int tiled_max_waves() {
-    return (limbs<R>::P == 4 ? RPL == 1 : limbs<R>::P * RPL <= 8) ? 16 : 8;
-}
-
 // Panel k0..k1-1 of problem blockIdx.x; blockDim.x = 64 (k1 - k0).  The
 // columns before k0 have been projected out of every panel column already.
 template <class R, int RPL>
 __global__ __launch_bounds__((64 * tiled_max_waves<R, RPL>())) void k_mgs_tpanel(MgsArgs a, int k0,
-                                                                                 int k1, int *sing) {
-    constexpr int P = limbs<R>::P;
-    constexpr int W = 2 * P;
+                                                                                   int k1, int *sing) {
     extern __shared__ double qbuf[];  // [N][W]: the newest q_k
-    __shared__ int s_bad;
     const int b = blockIdx.x;
     if (!problem_live(a, b) || sing[b]) return;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, N = a.N;
-    const int j = k0 + w;
-    double *aj = col_ptr(a, b, j);
-    cx<R> v[RPL];
-    wcol_load<R, RPL>(v, aj, N, lane);
-    for (int k = k0; k < k1; ++k) {
-        if (j == k) {
-            R s = rmake<R>(0.0);
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) {
-                const int i = lane + 64 * r;
-                if (i < N) s = r == 0 ? cnorm2(v[r]) : add(s, cnorm2(v[r]));
-            }
-            s = wave_rsum(s);
-            // every lane holds the same sum, so the same r_kk and 1/r_kk
-            const R rkk = sqrt(s);
-            const bool bad = !(lead(rkk) > 0.0) || !rfinite(rkk);
-            if (!bad) {
-                const R iv = div(rmake<R>(1.0), rkk);
-#pragma unroll
-                for (int r = 0; r < RPL; ++r) v[r] = cscale(iv, v[r]);
-                wcol_store<R, RPL>(v, qbuf, N, lane);
-                wcol_store<R, RPL>(v, aj, N, lane);
-                if (lane == 0) {
-                    rstore(a.inv + (size_t)b * a.inv_pstride + (size_t)k * P, iv);
-                    const cx<R> rc{rkk, rmake<R>(0.0)};
-                    cstore(a.R + (size_t)b * a.R_pstride + ((size_t)k * a.n + k) * W, rc);
-                }
-            }
-            if (lane == 0) s_bad = bad ? 1 : 0;
-        }
-        __syncthreads();
-        if (s_bad) {
-            if (threadIdx.x == 0) sing[b] = 1;
-            return;
-        }
-        if (j > k) {
-            const cx<R> rv = wcol_dot<R, RPL>(qbuf, v, N, lane);
-            if (lane == 0) cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * a.n + k) * W, rv);
-            wcol_axpy<R, RPL>(qbuf, v, rv, N, lane);
-        }
-        __syncthreads();
-    }
+    tiled_panel<R, RPL>(problem_of(a, b), k0, k1, sing + b, qbuf);
 }
 
-// Columns j >= k1 (the right-hand side j = n included), four per workgroup:
-// the projections k0..k1-1 in order.
+// Columns j >= k1 (the right-hand side j = n included), four per workgroup.
 template <class R, int RPL>
 __global__ __launch_bounds__(BT) void k_mgs_ttrail(MgsArgs a, int k0, int k1, int *sing) {
-    constexpr int W = 2 * limbs<R>::P;
     const int b = blockIdx.y;
     if (!problem_live(a, b) || sing[b]) return;
-    const int lane = threadIdx.x & 63, N = a.N;
     const int j = k1 + 4 * (int)blockIdx.x + (int)(threadIdx.x >> 6);
     if (j > a.n) return;
-    double *aj = col_ptr(a, b, j);
-    cx<R> v[RPL];
-    wcol_load<R, RPL>(v, aj, N, lane);
-    for (int k = k0; k < k1; ++k) {
-        const double *qk = col_ptr(a, b, k);
-        const cx<R> rv = wcol_dot<R, RPL>(qk, v, N, lane);
-        if (lane == 0) cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * a.n + k) * W, rv);
-        wcol_axpy<R, RPL>(qk, v, rv, N, lane);
-    }
-    wcol_store<R, RPL>(v, aj, N, lane);
+    tiled_trail<R, RPL>(problem_of(a, b), k0, k1, j);
 }
 
-// rows per lane of the tiled variant for N rows in precision P, 0 when the
-// columns do not fit in registers
-int mgs_tiled_rpl(int N, int P) {
-    const int need = (N + 63) / 64;
-    const int cap = P == 4 ? 4 : 8;
-    int rpl = 1;
-    while (rpl < need) rpl <<= 1;
-    return rpl <= cap ? rpl : 0;
-}
+int mgs_tiled_rpl(int N, int P) { return tiled_rpl(N, P); }
 
 static int g_panel = 16;
 

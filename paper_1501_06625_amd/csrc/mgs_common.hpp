@@ -321,4 +321,138 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
     mgs_epilogue<R>(p, s_flag != 0);
 }
 
+// Register-resident form of mgs_wg, for problems with N <= GRP * RPL rows and
+// n + 1 <= NGRP * CPG columns.  Column j belongs to lane group j % NGRP (its
+// slot j / NGRP); lane l of the group holds rows l, l + GRP, ... of each of
+// its columns in registers for the whole factorisation.  At step k the owner
+// of column k forms r_kk and 1/r_kk from the norm it computed at step k - 1,
+// scales its column into q_k and writes q_k to LDS; after one barrier every
+// group projects q_k out of its columns j > k, the owner of column k + 1
+// forming that column's norm right after its update.  Each element sees the
+// same operations as in mgs_wg and every reduction runs over the same rows in
+// the same order with the same butterfly, so the results are bitwise those of
+// mgs_wg; [A | b] is read once and only R (and Q for a plain solve) written.
+template <class R, int GRP, int RPL, int CPG>
+HCN_DEV void mgs_reg(const MgsProblem &p) {
+    constexpr int P = limbs<R>::P;
+    constexpr int W = 2 * P;
+    constexpr int NGRP = MGS_THREADS / GRP;
+    __shared__ double s_q[2][GRP * RPL * W];
+    __shared__ int s_flag;
+    const int tid = threadIdx.x;
+    const int g = tid / GRP;
+    const int lane = tid % GRP;
+    const int N = p.N, n = p.n;
+
+    if (p.mode == MGS_NEWTON_FIG2 || p.mode == MGS_MIXED_SOLVE) {
+        if (tid == 0) s_flag = p.mode == MGS_NEWTON_FIG2 ? fig2_decide(p) : !p.st->c_active;
+        __syncthreads();
+        if (s_flag) return;
+    }
+    auto col = [&](int j) -> double * { return j < n ? p.A + (size_t)j * p.A_cstride : p.bcol; };
+    cx<R> v[CPG][RPL];
+#pragma unroll
+    for (int c = 0; c < CPG; ++c) {
+        const int j = g + c * NGRP;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + r * GRP;
+            v[c][r] = (j <= n && i < N) ? cload<R>(col(j) + (size_t)i * W) : czero<R>();
+        }
+    }
+    // ||column||^2 over this lane's rows, then the group butterfly
+    auto norm2 = [&](const cx<R>(&u)[RPL]) -> R {
+        R t = rmake<R>(0.0);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r)
+            if (lane + r * GRP < N) t = r == 0 ? cnorm2(u[r]) : add(t, cnorm2(u[r]));
+        return group_sum<R, GRP>(t, lane);
+    };
+    R pend = rmake<R>(0.0);  // the norm of this group's next column
+    if (g == 0) pend = norm2(v[0]);
+    if (tid == 0) s_flag = 0;
+    __syncthreads();
+
+    for (int k = 0; k < n; ++k) {
+        double *q = s_q[k & 1];
+        if (g == k % NGRP) {
+            const int kc = k / NGRP;
+            const R rkk = sqrt(pend);
+            const bool bad = !(lead(rkk) > 0.0) || !rfinite(rkk);
+            if (!bad) {
+                const R iv = div(rmake<R>(1.0), rkk);
+#pragma unroll
+                for (int c = 0; c < CPG; ++c) {
+                    if (c != kc) continue;
+#pragma unroll
+                    for (int r = 0; r < RPL; ++r) {
+                        v[c][r] = cscale(iv, v[c][r]);
+                        cstore(q + (size_t)(lane + r * GRP) * W, v[c][r]);
+                    }
+                }
+                if (lane == 0) {
+                    rstore(p.inv + (size_t)k * P, iv);
+                    const cx<R> rc{rkk, rmake<R>(0.0)};
+                    cstore(p.R + ((size_t)k * n + k) * W, rc);
+                }
+            } else if (lane == 0) {
+                s_flag = 1;
+            }
+        }
+        __syncthreads();
+        if (s_flag) break;
+#pragma unroll
+        for (int c = 0; c < CPG; ++c) {
+            const int j = g + c * NGRP;
+            if (j <= k || j > n) continue;
+            cx<R> acc = czero<R>();
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                if (lane + r * GRP < N) {
+                    const cx<R> t = cmul_conj(cload<R>(q + (size_t)(lane + r * GRP) * W), v[c][r]);
+                    acc = r == 0 ? t : cadd(acc, t);
+                }
+            }
+            acc = group_csum<R, GRP>(acc, lane);
+            if (lane == 0) cstore(p.R + ((size_t)j * n + k) * W, acc);
+#pragma unroll
+            for (int r = 0; r < RPL; ++r)
+                if (lane + r * GRP < N)
+                    v[c][r] = csub(v[c][r], cmul(acc, cload<R>(q + (size_t)(lane + r * GRP) * W)));
+            if (j == k + 1 && j < n) pend = norm2(v[c]);
+        }
+    }
+    // a plain solve returns Q and the projected right-hand side in place
+    if (p.mode == MGS_SOLVE && !s_flag) {
+#pragma unroll
+        for (int c = 0; c < CPG; ++c) {
+            const int j = g + c * NGRP;
+            if (j > n) continue;
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+                const int i = lane + r * GRP;
+                if (i < N) cstore(col(j) + (size_t)i * W, v[c][r]);
+            }
+        }
+    }
+    __syncthreads();
+    mgs_epilogue<R>(p, s_flag != 0);
+}
+
+// rows per lane and columns per group of mgs_reg for a problem (0 when it
+// does not fit the register budget: at most 8 complex numbers per lane in
+// DD and FP64; in QD at most 4 and one column per group)
+HCN_DEV __host__ inline void mgs_reg_shape(int N, int n, int P, int grp, int *rpl, int *cpg) {
+    const int ngrp = MGS_THREADS / grp;
+    auto up = [](int x) { return x <= 1 ? 1 : x <= 2 ? 2 : x <= 4 ? 4 : 8; };
+    const int r = up((N + grp - 1) / grp), c = up((n + 1 + ngrp - 1) / ngrp);
+    const int cap = P == 4 ? 4 : 8;
+    if (r * c > cap || r > 4 || c > 4 || (P == 4 && c > 1)) {
+        *rpl = *cpg = 0;
+    } else {
+        *rpl = r;
+        *cpg = c;
+    }
+}
+
 }  // namespace hcn

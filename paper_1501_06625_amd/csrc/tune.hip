@@ -1,8 +1,9 @@
 // tune.hip -- kernel-variant table and the autotuner.
 //
 // Choices: the lane-group width of the one-workgroup MGS (8, 16 or 32 lanes
-// per column) and whether [A | b] is staged in LDS, per precision and row
-// count bucket.  hcn_autotune times a Newton step of a given system for every
+// per column) and where [A | b] lives during the factorisation (0 global
+// memory, 1 staged in LDS, 2 held in registers by the owning lane groups),
+// per precision and row count bucket.  hcn_autotune times a Newton step of a given system for every
 // choice (HIP events on the caller's stream) and keeps the fastest; the
 // table can be saved to and loaded from a text file (one line per entry:
 // "P Nbucket group lds").  A choice depends only on (P, N), never on what
@@ -58,7 +59,7 @@ extern "C" {
 
 int hcn_tune_set(int P, int N, int mgs_group, int mgs_lds) {
     if ((P != 1 && P != 2 && P != 4) || N < 1 ||
-        (mgs_group != 8 && mgs_group != 16 && mgs_group != 32) || (mgs_lds != 0 && mgs_lds != 1))
+        (mgs_group != 8 && mgs_group != 16 && mgs_group != 32) || mgs_lds < 0 || mgs_lds > 2)
         return HCN_EINVAL;
     tune_set(P, N, mgs_group, mgs_lds);
     return HCN_OK;
@@ -130,7 +131,10 @@ int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_gr
     double bms = 1e300;
     const bool lds_fits = mgs_lds_bytes(N, n, P) <= mgs_lds_limit();
     for (int grp : {8, 16, 32}) {
-        for (int lds = 0; lds <= (lds_fits ? 1 : 0); ++lds) {
+        int rpl = 0, cpg = 0;
+        mgs_reg_shape(N, n, P, grp, &rpl, &cpg);
+        for (int lds = 0; lds <= 2; ++lds) {
+            if ((lds == 1 && !lds_fits) || (lds == 2 && rpl == 0)) continue;
             tune_set(P, N, grp, lds);
             float ms = 0.0f;
             for (int pass = 0; pass < 2 && rc == HCN_OK; ++pass) {  // warm-up, then timed

@@ -63,10 +63,10 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_sys_degrees", "hcn_eval_ws_bytes", "hcn_eval_jac", "hcn_mgs_ws_bytes",
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
-           "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
+           "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_set_chunk_bytes", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
            "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load", "hcn_autotune",
            "hcn_batch_create", "hcn_batch_destroy", "hcn_batch_device_bytes",
-           "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_step",
+           "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_set_split", "hcn_batch_step",
            "hcn_batch_poll", "hcn_batch_result", "hcn_batch_run", "hcn_batch_counts",
            "hcn_server_create", "hcn_server_destroy", "hcn_server_last_error", "hcn_server_now",
            "hcn_server_capacity", "hcn_server_submit", "hcn_server_pump", "hcn_server_fetch",
@@ -103,6 +103,7 @@ def _load():
     lib.hcn_profile_enable.argtypes = [ci]
     lib.hcn_set_mgs_variant.argtypes = [ci]
     lib.hcn_set_mgs_panel.argtypes = [ci]
+    lib.hcn_set_chunk_bytes.argtypes = [sz]
     lib.hcn_newton_mixed_ws_bytes.argtypes = [vp, ci]
     lib.hcn_newton_mixed_ws_bytes.restype = sz
     lib.hcn_newton_mixed.argtypes = lib.hcn_newton.argtypes
@@ -120,6 +121,7 @@ def _load():
     lib.hcn_batch_last_error.restype = ctypes.c_char_p
     lib.hcn_batch_add.argtypes = [vp, ci, vp, vp, vp, vp]
     lib.hcn_batch_release.argtypes = [vp, ci]
+    lib.hcn_batch_set_split.argtypes = [vp, ci]
     lib.hcn_batch_step.argtypes = [vp, ci, vp]
     lib.hcn_batch_poll.argtypes = [vp, vp, vp]
     lib.hcn_batch_result.argtypes = [vp, ci, vp, vp, vp]
@@ -401,6 +403,11 @@ def set_mgs_panel(T: int) -> None:
     _check(_lib.hcn_set_mgs_panel(int(T)))
 
 
+def set_chunk_bytes(nbytes: int) -> None:
+    """Point chunking of the Newton and tracking launches (see hcn_set_chunk_bytes)."""
+    _check(_lib.hcn_set_chunk_bytes(int(nbytes)))
+
+
 def tune_set(P: int, N: int, mgs_group: int, mgs_lds: int) -> None:
     """Kernel-variant choice for problems of precision P and N rows."""
     _check(_lib.hcn_tune_set(P, N, mgs_group, mgs_lds))
@@ -451,7 +458,8 @@ class Batch:
     """Slot table of paths of many systems (hcn_batch_*)."""
 
     def __init__(self, P: int, capacity: int, max_n: int, max_nslots: int,
-                 max_systems: int = 256, relax_k: int = 1, mixed: bool = False, **track_kw):
+                 max_systems: int = 256, relax_k: int = 1, mixed: bool = False,
+                 split_n: int = 0, **track_kw):
         self.P = P
         self.capacity = capacity
         self.prm = track_params(P, **track_kw)
@@ -460,6 +468,8 @@ class Batch:
                                       max_systems, ctypes.byref(self.prm), relax_k,
                                       1 if mixed else 0))
         self.handle = h
+        if split_n:
+            _bcheck(_lib.hcn_batch_set_split(h, int(split_n)))
         self._keep = {}
         self.device = torch.device("cuda", torch.cuda.current_device())
 
