@@ -25,6 +25,13 @@ import sys
 import threading
 import time
 
+# The serving leg runs one stream per lane (6 lanes).  HIP maps streams onto
+# GPU_MAX_HW_QUEUES hardware queues (4 by default), and streams that share a
+# queue run in order, which would make small systems wait for large ones; the
+# variable is read when the HIP runtime starts, so it is set before torch.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

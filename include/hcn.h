@@ -155,11 +155,12 @@ int hcn_set_mgs_panel(int T);
 
 /* Point chunking (process-wide) of hcn_newton_step, hcn_newton,
  * hcn_newton_mixed and hcn_track_paths: each Newton iteration runs its
- * evaluation, summation and solve launches over chunks of points whose
- * monomial scratch, [J | -h] and R take about `bytes` (a multiple of 64
- * points, at least 64), so that what one launch writes is still in the
- * last-level cache when the next reads it.  0 (the default) runs every launch
- * over the whole batch.  Results are bitwise the same for every setting. */
+ * monomial and summation launches over chunks of points whose monomial
+ * scratch takes about `bytes` (a multiple of 64 points, at least 64), so that
+ * the scratch one launch writes is still in the last-level cache when the
+ * next reads it; the solve covers the whole batch.  0 (the default) runs
+ * every launch over the whole batch.  Results are bitwise the same for every
+ * setting. */
 int hcn_set_chunk_bytes(size_t bytes);
 
 /* Kernel-variant table used by the one-workgroup MGS: lane-group width
@@ -282,8 +283,10 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B,
  * Batches: a slot table of up to `capacity` paths of any number of systems
  * of one precision, tracked together (Fig. 3 per path, the step size of
  * each path its own).  Every kernel launch covers every occupied slot; the
- * step is captured once into a HIP graph and replayed; the work lists are
- * rebuilt when slots are added or released.  A path's arithmetic depends
+ * step is captured once into a HIP graph (on the caller's stream, or for
+ * the legacy null stream on a stream of the batch's own joined to it by
+ * events) and replayed; the work lists are rebuilt when slots are added or
+ * released.  A path's arithmetic depends
  * only on its own system, start point, gamma and the tuning table, so its
  * result is bitwise the same alone and in any mix.  Sizing: every system
  * added must have N == n <= max_n and at most max_nslots evaluation slots
@@ -359,7 +362,10 @@ int hcn_batch_run(hcn_batch b, int chunk, void *stream);
  * launches, and a result does not depend on the mix; systems with n >= 48
  * solve with the tiled MGS across workgroups (hcn_batch_set_split).
  * serial != 0 runs one path at a time, oldest request first (a baseline).
- * Times are seconds on the server's monotonic clock (hcn_server_now).
+ * Times are seconds on the server's monotonic clock (hcn_server_now).  The
+ * lanes progress independently only when their streams land on different
+ * hardware queues: HIP's GPU_MAX_HW_QUEUES (default 4) should be at least
+ * the number of lanes plus the caller's streams.
  * --------------------------------------------------------------------- */
 
 typedef struct hcn_server_s *hcn_server;

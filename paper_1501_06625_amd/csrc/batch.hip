@@ -304,9 +304,8 @@ struct hcn_batch_s {
     int32_t *h_running = nullptr, *h_done = nullptr;
     bool dirty = true;
     hipGraphExec_t exec = nullptr;
-    // graphs are captured and replayed on the batch's own stream (capture is
-    // not possible on the legacy null stream), joined to the caller's stream
-    // with events on both sides
+    // for callers on the legacy null stream (which cannot be captured) the
+    // graph runs on a stream of the batch's own, created at first use
     hipStream_t own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
 };
@@ -592,15 +591,6 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
         delete b;
         return bfail(HCN_ENOMEM, "hcn_batch_create: pinned allocation failed");
     }
-    if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
-        (void)hipHostFree(b->h_running);
-        (void)hipHostFree(b->h_done);
-        (void)hipFree(b->dmem);
-        delete b;
-        return bfail(HCN_EDEVICE, "hcn_batch_create: stream or event creation failed");
-    }
     if (P == 2)
         set_lds_attributes<dd>();
     else
@@ -693,27 +683,36 @@ int hcn_batch_step(hcn_batch b, int steps, void *stream) {
         if (rc) return rc;
     }
     if (b->n_slots == 0 || steps == 0) return HCN_OK;
-    hipStream_t own = b->own;
+    // the graph is captured and replayed on the caller's stream; the legacy
+    // null stream cannot be captured, so its callers go through the batch's
+    // own stream, joined with events on both sides
+    if (!s && !b->own) {
+        if (hipStreamCreateWithFlags(&b->own, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess)
+            return bfail(HCN_EDEVICE, "hcn_batch_step: stream or event creation failed");
+    }
+    hipStream_t run = s ? s : b->own;
     if (!b->exec) {
         hipGraph_t g = nullptr;
-        if (hipStreamBeginCapture(own, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        if (hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return bfail(HCN_EDEVICE, "hcn_batch_step: capture begin failed");
-        const int e = b->P == 2 ? enqueue_step<dd>(b, own) : enqueue_step<qd>(b, own);
-        const hipError_t ec = hipStreamEndCapture(own, &g);
+        const int e = b->P == 2 ? enqueue_step<dd>(b, run) : enqueue_step<qd>(b, run);
+        const hipError_t ec = hipStreamEndCapture(run, &g);
         if (e || ec != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_step: capture failed");
         const hipError_t ei = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (ei != hipSuccess) return bfail(HCN_EDEVICE, "hcn_batch_step: instantiate failed");
     }
-    if (hipEventRecord(b->ev_in, s) != hipSuccess || hipStreamWaitEvent(own, b->ev_in, 0) != hipSuccess)
+    if (!s && (hipEventRecord(b->ev_in, s) != hipSuccess || hipStreamWaitEvent(run, b->ev_in, 0) != hipSuccess))
         return bfail(HCN_EDEVICE, "hcn_batch_step: stream join failed");
     {
-        ProfScope prof("batch_step", own);
+        ProfScope prof("batch_step", run);
         for (int q = 0; q < steps; ++q)
-            if (hipGraphLaunch(b->exec, own) != hipSuccess)
+            if (hipGraphLaunch(b->exec, run) != hipSuccess)
                 return bfail(HCN_EDEVICE, "hcn_batch_step: graph launch failed");
     }
-    if (hipEventRecord(b->ev_out, own) != hipSuccess || hipStreamWaitEvent(s, b->ev_out, 0) != hipSuccess)
+    if (!s && (hipEventRecord(b->ev_out, run) != hipSuccess || hipStreamWaitEvent(s, b->ev_out, 0) != hipSuccess))
         return bfail(HCN_EDEVICE, "hcn_batch_step: stream join failed");
     return HCN_OK;
 }

@@ -93,14 +93,14 @@ int enqueue_mgs(int P, const MgsArgs &a, int *ints, hipStream_t s) {
     return enqueue_mgs_variant(P, a, mgs_variant_for(a.n, a.B), ints, s);
 }
 
-// Points per chunk: the monomial scratch, [J | -h] and R of one chunk take
-// about g_chunk_bytes, so that what one launch writes is still in the
-// last-level cache when the next launch reads it.  A multiple of 64, at
-// least 64, at most B.
+// Points per chunk of the evaluation: the monomial scratch of one chunk
+// takes about g_chunk_bytes, so that what the monomial launch writes is
+// still in the last-level cache when the summation reads it (the solve runs
+// over the whole batch, which it needs to fill the GPU).  A multiple of 64,
+// at least 64, at most B.
 int chunk_points(const SysView &v, int B, int RP) {
     if (g_chunk_bytes == 0) return B;
-    const size_t per =
-        ((size_t)v.nslots + 2 * (size_t)(v.n + 1) * v.N) * 2 * (size_t)RP * sizeof(double);
+    const size_t per = (size_t)v.nslots * 2 * (size_t)RP * sizeof(double);
     long c = (long)(g_chunk_bytes / std::max<size_t>(per, 1));
     c = std::max<long>(64, c / 64 * 64);
     return (int)std::min<long>(c, B);
@@ -488,16 +488,13 @@ int enqueue_eval_aug(const SysView &v, int B, const double *x, const Homotopy &h
 // whatever the chunk.
 int enqueue_newton_iter(const SysView &v, int B, const double *x, const Homotopy &hom,
                         const NewtonWs &w, const PathState *st, const MgsArgs &a, hipStream_t s) {
-    const int variant = mgs_variant_for(v.n, B);
     const int C = chunk_points(v, B, v.P);
     for (int b0 = 0; b0 < B; b0 += C) {
-        const int Bc = std::min(C, B - b0);
-        const int rc = enqueue_eval_aug(v, B, x, hom, w, st, s, b0, Bc);
+        const int rc = enqueue_eval_aug(v, B, x, hom, w, st, s, b0, std::min(C, B - b0));
         if (rc) return rc;
-        const int e = enqueue_mgs_variant(v.P, chunk_of(a, b0, Bc), variant, w.ints, s);
-        if (e) return dev_fail(e, "solve launch");
     }
-    return HCN_OK;
+    const int e = enqueue_mgs(v.P, a, w.ints, s);
+    return e ? dev_fail(e, "solve launch") : HCN_OK;
 }
 
 MgsArgs newton_mgs_args(const SysView &v, int B, const NewtonWs &w, double *x, int mode) {
@@ -871,29 +868,30 @@ int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B, const
     sj.J_pstride = (long)(v.n + 1) * colN;
     const MonArgs mr = mon_args(v, B, x, w.sc_ext, v.P, w.st, 1);
     const MonArgs mj = mon_args(v, B, x, w.sc64, 1, w.st, 0);
-    const int variant = mgs_variant_for(v.n, B);
-    const int C = chunk_points(v, B, 1);
+    const int Cr = chunk_points(v, B, v.P), Cj = chunk_points(v, B, 1);
     for (int it = 0; it < prm->max_iter; ++it) {
-        for (int b0 = 0; b0 < B; b0 += C) {
-            const int Bc = std::min(C, B - b0);
-            const MgsArgs ac = chunk_of(a, b0, Bc);
-            // residual in extended precision; its rounding is the right-hand side
+        // residual in extended precision; its rounding is the right-hand side
+        for (int b0 = 0; b0 < B; b0 += Cr) {
+            const int Bc = std::min(Cr, B - b0);
             e = launch_mon(v.P, chunk_of(mr, b0, Bc), s);
             if (e) return dev_fail(e, "hcn_newton_mixed: residual launch");
             e = launch_sum(v.P, chunk_of(sr, b0, Bc), s);
             if (e) return dev_fail(e, "hcn_newton_mixed: residual sum launch");
-            e = launch_fig2_pre(ac, s);
-            if (e) return dev_fail(e, "hcn_newton_mixed: test launch");
-            // the Jacobian in FP64 at the leading limbs of x
+        }
+        e = launch_fig2_pre(a, s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: test launch");
+        // the Jacobian in FP64 at the leading limbs of x
+        for (int b0 = 0; b0 < B; b0 += Cj) {
+            const int Bc = std::min(Cj, B - b0);
             e = launch_mon(1, chunk_of(mj, b0, Bc), s);
             if (e) return dev_fail(e, "hcn_newton_mixed: Jacobian launch");
             e = launch_sum(1, chunk_of(sj, b0, Bc), s);
             if (e) return dev_fail(e, "hcn_newton_mixed: Jacobian sum launch");
-            e = enqueue_mgs_variant(1, ac, variant, w.ints, s);
-            if (e) return dev_fail(e, "hcn_newton_mixed: solve launch");
-            e = launch_mixed_update(v.P, ac, s);
-            if (e) return dev_fail(e, "hcn_newton_mixed: update launch");
         }
+        e = enqueue_mgs(1, a, w.ints, s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: solve launch");
+        e = launch_mixed_update(v.P, a, s);
+        if (e) return dev_fail(e, "hcn_newton_mixed: update launch");
     }
     e = launch_newton_finish(B, w.st, norms, status, iters, s);
     return dev_fail(e, "hcn_newton_mixed: finish launch");
