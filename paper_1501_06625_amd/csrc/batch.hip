@@ -72,15 +72,25 @@ __global__ void k_b_end(BatchDev d, const int *slots) {
     track_end_one<R>(d.prm, slot_path(d, slots[blockIdx.x]));
 }
 
-template <class R, int KB, int MODE>
+// UNI (every registered system mon_uniform): the workgroup first tabulates
+// the slot point's powers in LDS when its system has exponents above two
+template <class R, int KB, int MODE, bool UNI>
 __global__ __launch_bounds__(256) void k_b_mon(BatchDev d, const int2 *work) {
+    extern __shared__ double pows[];
     const int2 w = work[blockIdx.x];
     const int slot = w.x;
     if (!d.st[slot].c_active) return;
     const SysView &s = d.sys[d.slot_sys[slot]];
+    const double *xb = d.x + (size_t)slot * d.xs;
+    const bool table = UNI && s.max_e > 2;
+    if (table) {
+        stage_pows<R>(s, xb, d.P, pows);
+        __syncthreads();
+    }
+    const PointView pv{xb, 2 * d.P, d.P, table ? pows : nullptr};
     const int m = w.y * 256 + threadIdx.x;
     if (m >= s.nmon) return;
-    mon_one<R, KB, MODE>(s, m, d.x + (size_t)slot * d.xs, d.P, d.sc + (size_t)slot * d.scs);
+    mon_one<R, KB, MODE, UNI>(s, m, pv, d.sc + (size_t)slot * d.scs);
 }
 
 // what a sum launch forms: the full [J | -h] with its norm parts, the
@@ -314,16 +324,35 @@ extern "C" const char *hcn_batch_last_error(void) { return g_berr.c_str(); }
 
 namespace {
 
+template <class R, int MODE, bool UNI>
+void launch_b_mon_u(hcn_batch_s *b, size_t lds, hipStream_t s) {
+    const BatchDev &d = b->d;
+    constexpr int ML = MODE == MON_VALUES ? MON_VALUES : MON_FSLOT;
+    const dim3 g(b->n_mon), t(256);
+    switch (b->kb) {
+        case 4: hipLaunchKernelGGL((k_b_mon<R, 4, MODE, UNI>), g, t, lds, s, d, b->d_mon); break;
+        case 8: hipLaunchKernelGGL((k_b_mon<R, 8, MODE, UNI>), g, t, lds, s, d, b->d_mon); break;
+        case 16: hipLaunchKernelGGL((k_b_mon<R, 16, MODE, UNI>), g, t, lds, s, d, b->d_mon); break;
+        case 32: hipLaunchKernelGGL((k_b_mon<R, 32, ML, UNI>), g, t, lds, s, d, b->d_mon); break;
+        default: hipLaunchKernelGGL((k_b_mon<R, 64, ML, UNI>), g, t, lds, s, d, b->d_mon); break;
+    }
+}
+
 template <class R, int MODE>
 void launch_b_mon(hcn_batch_s *b, hipStream_t s) {
-    const BatchDev &d = b->d;
-    switch (b->kb) {
-        case 4: hipLaunchKernelGGL((k_b_mon<R, 4, MODE>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
-        case 8: hipLaunchKernelGGL((k_b_mon<R, 8, MODE>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
-        case 16: hipLaunchKernelGGL((k_b_mon<R, 16, MODE>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
-        case 32: hipLaunchKernelGGL((k_b_mon<R, 32, MODE == MON_VALUES ? MON_VALUES : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
-        default: hipLaunchKernelGGL((k_b_mon<R, 64, MODE == MON_VALUES ? MON_VALUES : MON_FSLOT>), dim3(b->n_mon), dim3(256), 0, s, d, b->d_mon); break;
+    // the power table of the largest registered system (each workgroup uses
+    // its own); the uniform form of the common factor when every system
+    // allows it (both forms give the same bits)
+    size_t lds = 0;
+    bool uni = !b->views.empty();
+    for (const SysView &v : b->views) {
+        lds = std::max(lds, mon_stage_bytes(v, limbs<R>::P));
+        if (!mon_uniform(v, limbs<R>::P)) uni = false;
     }
+    if (uni)
+        launch_b_mon_u<R, MODE, true>(b, lds, s);
+    else
+        launch_b_mon_u<R, MODE, false>(b, lds, s);
 }
 
 template <class R, int RPL>

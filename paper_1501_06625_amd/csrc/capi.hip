@@ -328,6 +328,8 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
     v.P = P;
     v.nmon = nmon;
     v.max_k = max_k;
+    v.max_e = 1;
+    for (int q = 0; q < npairs; ++q) v.max_e = std::max(v.max_e, (int)exp[q]);
     v.nslots = (int)nslots;
     v.mon_k = d_k;
     v.mon_slot = d_slot;
@@ -900,6 +902,11 @@ int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B, const
 int hcn_set_mgs_variant(int variant) {
     if (variant < 0 || variant > 4) return fail(HCN_EINVAL, "hcn_set_mgs_variant: 0..4");
     g_mgs_variant = variant;
+    return HCN_OK;
+}
+
+int hcn_set_mon_uniform(int on) {
+    set_mon_uniform(on != 0);
     return HCN_OK;
 }
 

@@ -14,14 +14,23 @@
 
 namespace hcn {
 
-template <class R, int KB, int MODE>
+// UNI (mon_uniform): the workgroup first tabulates its point's powers in
+// LDS when some exponent exceeds two (dynamic LDS, mon_stage_bytes).
+template <class R, int KB, int MODE, bool UNI>
 __global__ __launch_bounds__(256) void k_mon(MonArgs a) {
+    extern __shared__ double pows[];
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= a.s.nmon) return;
+    const bool table = UNI && a.s.max_e > 2;
     for (int b = blockIdx.y; b < a.B; b += gridDim.y) {
         if (a.st && !a.st[b].c_active) continue;
-        mon_one<R, KB, MODE>(a.s, m, a.x + (size_t)b * a.x_pstride, a.xP,
-                             a.scratch + (size_t)b * a.sc_pstride);
+        const double *xb = a.x + (size_t)b * a.x_pstride;
+        if (table) {
+            stage_pows<R>(a.s, xb, a.xP, pows);
+            __syncthreads();
+        }
+        const PointView pv{xb, 2 * a.xP, a.xP, table ? pows : nullptr};
+        if (m < a.s.nmon) mon_one<R, KB, MODE, UNI>(a.s, m, pv, a.scratch + (size_t)b * a.sc_pstride);
+        if (table) __syncthreads();
     }
 }
 
@@ -57,17 +66,33 @@ static int kbucket(int max_k) {
     return 64;
 }
 
-template <class R, int KB>
-static void mon_kb(const MonArgs &a, dim3 grid, hipStream_t stream) {
+static bool g_mon_uniform = true;
+
+bool mon_uniform_enabled() { return g_mon_uniform; }
+void set_mon_uniform(bool on) { g_mon_uniform = on; }
+
+template <class R, int KB, bool UNI>
+static void mon_kb_u(const MonArgs &a, dim3 grid, size_t lds, hipStream_t stream) {
     // forward products in registers where they fit (DD up to 16, FP64 up to
     // 32 variables); QD and longer products park them in their output slots
     constexpr bool freg = (limbs<R>::P == 2 && KB <= 16) || (limbs<R>::P == 1 && KB <= 32);
     if (a.values_only)
-        hipLaunchKernelGGL((k_mon<R, KB, MON_VALUES>), grid, dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((k_mon<R, KB, MON_VALUES, UNI>), grid, dim3(256), lds, stream, a);
     else if (freg)
-        hipLaunchKernelGGL((k_mon<R, KB, MON_FREG>), grid, dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((k_mon<R, KB, MON_FREG, UNI>), grid, dim3(256), lds, stream, a);
     else
-        hipLaunchKernelGGL((k_mon<R, KB, MON_FSLOT>), grid, dim3(256), 0, stream, a);
+        hipLaunchKernelGGL((k_mon<R, KB, MON_FSLOT, UNI>), grid, dim3(256), lds, stream, a);
+}
+
+template <class R, int KB>
+static void mon_kb(const MonArgs &a, dim3 grid, hipStream_t stream) {
+    if constexpr (limbs<R>::P <= 2) {
+        if (mon_uniform(a.s, limbs<R>::P)) {
+            mon_kb_u<R, KB, true>(a, grid, mon_stage_bytes(a.s, limbs<R>::P), stream);
+            return;
+        }
+    }
+    mon_kb_u<R, KB, false>(a, grid, 0, stream);
 }
 
 template <class R>

@@ -28,11 +28,56 @@ namespace hcn {
 
 enum { MON_FREG = 0, MON_FSLOT = 1, MON_VALUES = 2 };
 
+// The point a monomial kernel reads: variable v at x + v * stride, xP limbs
+// (at least those of the compute precision).  pows (LDS, or NULL when the
+// largest exponent is at most 2): pows + ((j - 2) n + v) W holds y_v^j for
+// 2 <= j < maxe, so that the common factor can be formed with the same
+// products in every lane (see mon_one).
+struct PointView {
+    const double *x;
+    int stride, xP;
+    const double *pows;
+};
+
 template <class R>
-HCN_DEV cx<R> load_y(const SysView &s, const double *xb, int xP, int p, int m) {
-    const int v = s.pos[(size_t)p * s.nmon + m];
-    return cload_s<R>(xb + (size_t)v * 2 * xP, xP);
+HCN_DEV cx<R> load_y(const SysView &s, const PointView &pv, int p, int m, int &v) {
+    v = s.pos[(size_t)p * s.nmon + m];
+    return cload_s<R>(pv.x + (size_t)v * pv.stride, pv.xP);
 }
+
+// the powers y^2 .. y^{maxe-1} of every variable of one point into LDS
+// (pows: (maxe - 2) n complex numbers in the compute precision);
+// y^j = y^{j-1} y, the products cpow_small forms
+template <class R>
+HCN_DEV void stage_pows(const SysView &s, const double *xb, int xP, double *pows) {
+    constexpr int W = 2 * limbs<R>::P;
+    for (int v = threadIdx.x; v < s.n; v += blockDim.x) {
+        const cx<R> y = cload_s<R>(xb + (size_t)v * 2 * xP, xP);
+        cx<R> r = y;
+        for (int j = 2; j < s.max_e; ++j) {
+            r = cmul(r, y);
+            cstore(pows + ((size_t)(j - 2) * s.n + v) * W, r);
+        }
+    }
+}
+
+// LDS bytes of stage_pows for system s in compute precision RP; 0 when no
+// power is needed (largest exponent at most 2) or the table would not fit
+// the budget of one workgroup
+HCN_DEV __host__ size_t mon_stage_bytes(const SysView &s, int RP) {
+    if (s.max_e <= 2) return 0;
+    const size_t b = (size_t)(s.max_e - 2) * s.n * 2 * RP * sizeof(double);
+    return b <= 32 * 1024 ? b : 0;
+}
+
+// whether the monomial kernels use the uniform form of the common factor:
+// DD or FP64, some exponent above one, and the power table staged if needed
+// (host side: also the process-wide switch mon_uniform_enabled)
+HCN_DEV __host__ bool mon_uniform_fits(const SysView &s, int RP) {
+    return RP <= 2 && s.max_e >= 2 && (s.max_e == 2 || mon_stage_bytes(s, RP) > 0);
+}
+bool mon_uniform_enabled();
+inline bool mon_uniform(const SysView &s, int RP) { return mon_uniform_enabled() && mon_uniform_fits(s, RP); }
 
 // a d for the exponent a of a variable: 1 leaves d, 2 doubles every limb
 // (exact), larger exponents multiply by a double
@@ -54,9 +99,18 @@ HCN_DEV cx<R> cpow_small(const cx<R> &y, int e) {
 // MODE: MON_FREG keeps the forward products in registers (KB-1 of them);
 // MON_FSLOT parks them in the output slots of the partials they precede and
 // reads them back in the backward sweep; MON_VALUES forms values only.
-template <class R, int KB, int MODE>
-HCN_DEV void mon_one(const SysView &s, int m, const double *xb, int xP, double *out) {
+//
+// Uniform form (mon_uniform: DD and FP64, some exponent > 1):
+// exponents differ from lane to lane, so a branch per variable would run
+// both ways for the whole wavefront.  Instead every lane multiplies the
+// common factor by y^{a-1} at every position, with y^0 = 1 (a product by 1
+// is exact for a normalised DD / FP64 number) and y^{a-1} from the staged
+// table, and scales every partial by a with mul_d (exact for a = 1, 2):
+// the same bits as the branching form, in the same operations for all lanes.
+template <class R, int KB, int MODE, bool UNI = false>
+HCN_DEV void mon_one(const SysView &s, int m, const PointView &pv, double *out) {
     constexpr int W = 2 * limbs<R>::P;
+    constexpr bool uni = UNI && limbs<R>::P <= 2;  // callers: mon_uniform
     const int k = s.mon_k[m];
     const int slot = s.mon_slot[m];
     const int stride = s.mon_stride[m];
@@ -65,15 +119,25 @@ HCN_DEV void mon_one(const SysView &s, int m, const double *xb, int xP, double *
         cstore(out + (size_t)slot * W, c);
         return;
     }
+    auto escale = [&](const cx<R> &d, int a) -> cx<R> {
+        if constexpr (uni) return cscale_d(d, (double)a);
+        return exp_scale(d, a);
+    };
     cx<R> F[MODE == MON_FREG ? (KB > 1 ? KB - 1 : 1) : 1];
     cx<R> Flast = czero<R>(), ylast = czero<R>(), pc = czero<R>();
     bool has_pc = false;
 #pragma unroll
     for (int p = 0; p < KB; ++p) {
         if (p < k) {
-            const cx<R> y = load_y<R>(s, xb, xP, p, m);
+            int v;
+            const cx<R> y = load_y<R>(s, pv, p, m, v);
             const int e = s.ex[(size_t)p * s.nmon + m];
-            if (e >= 2) {
+            if constexpr (uni) {
+                cx<R> pw = y;
+                if (e >= 3) pw = cload<R>(pv.pows + ((size_t)(e - 3) * s.n + v) * W);
+                if (e == 1) pw = cone<R>();
+                pc = (p == 0) ? pw : cmul(pc, pw);
+            } else if (e >= 2) {
                 const cx<R> pw = cpow_small(y, e - 1);
                 pc = has_pc ? cmul(pc, pw) : pw;
                 has_pc = true;
@@ -91,10 +155,10 @@ HCN_DEV void mon_one(const SysView &s, int m, const double *xb, int xP, double *
             }
         }
     }
-    const cx<R> cp = has_pc ? cmul(c, pc) : c;
+    const cx<R> cp = uni ? cmul(c, pc) : (has_pc ? cmul(c, pc) : c);
     if (k == 1) {
         cstore(out + (size_t)slot * W, cmul(cp, ylast));
-        if (MODE != MON_VALUES) cstore(out + (size_t)(slot + stride) * W, exp_scale(cp, s.ex[m]));
+        if (MODE != MON_VALUES) cstore(out + (size_t)(slot + stride) * W, escale(cp, s.ex[m]));
         return;
     }
     // the coefficient rides on the backward product: B' = c' y_{k-1}
@@ -102,7 +166,7 @@ HCN_DEV void mon_one(const SysView &s, int m, const double *xb, int xP, double *
     cstore(out + (size_t)slot * W, cmul(Flast, Bk));
     if (MODE == MON_VALUES) return;
     cstore(out + (size_t)(slot + k * stride) * W,
-           exp_scale(cmul(cp, Flast), s.ex[(size_t)(k - 1) * s.nmon + m]));
+           escale(cmul(cp, Flast), s.ex[(size_t)(k - 1) * s.nmon + m]));
 #pragma unroll
     for (int p = KB - 2; p >= 1; --p) {
         if (p <= k - 2) {
@@ -113,11 +177,12 @@ HCN_DEV void mon_one(const SysView &s, int m, const double *xb, int xP, double *
                 Fpm1 = cload<R>(out + (size_t)(slot + (p + 1) * stride) * W);
             }
             cstore(out + (size_t)(slot + (p + 1) * stride) * W,
-                   exp_scale(cmul(Fpm1, Bk), s.ex[(size_t)p * s.nmon + m]));
-            Bk = cmul(Bk, load_y<R>(s, xb, xP, p, m));
+                   escale(cmul(Fpm1, Bk), s.ex[(size_t)p * s.nmon + m]));
+            int v;
+            Bk = cmul(Bk, load_y<R>(s, pv, p, m, v));
         }
     }
-    cstore(out + (size_t)(slot + stride) * W, exp_scale(Bk, s.ex[m]));
+    cstore(out + (size_t)(slot + stride) * W, escale(Bk, s.ex[m]));
 }
 
 template <class R>

@@ -26,6 +26,7 @@ namespace hcn {
 // input monomial order.
 struct SysView {
     int N, n, P, nmon, max_k, nslots;
+    int max_e;  // largest exponent
     const int32_t *mon_k;
     const int32_t *mon_slot;
     const int32_t *mon_stride;
@@ -128,6 +129,7 @@ struct SumArgs {
 int launch_mon(int RP, const MonArgs &a, hipStream_t stream);
 int launch_sum(int RP, const SumArgs &a, hipStream_t stream);
 int sum_nparts(const SysView &s, int jac);
+void set_mon_uniform(bool on);
 int launch_mgs(int RP, const MgsArgs &a, hipStream_t stream);
 // multi-workgroup MGS for large single problems: variant 2 right-looking
 // (one launch per column step), 3 column-resident (cooperative); ints_dev

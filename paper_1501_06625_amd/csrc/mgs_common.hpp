@@ -182,31 +182,55 @@ HCN_DEV void mgs_epilogue(const MgsProblem &p, bool singular) {
     }
 }
 
-HCN_DEV double gshfl(double v, int m) { return __shfl_xor(v, m); }
-HCN_DEV dd gshfl(const dd &v, int m) { return dd{gshfl(v.hi, m), gshfl(v.lo, m)}; }
-HCN_DEV qd gshfl(const qd &v, int m) {
-    return qd{gshfl(v.c0, m), gshfl(v.c1, m), gshfl(v.c2, m), gshfl(v.c3, m)};
+// The partner's value at butterfly level M (lanes l and l ^ M).  Inside a
+// row of 16 lanes by DPP: quad_perm for M = 1, 2; for M = 4 and 8 the
+// half-row and row mirrors (l <-> 7 - l, l <-> 15 - l), which reach a lane
+// of the same quad / half-row as l ^ M and so the same value once the
+// earlier levels have made every quad / half-row uniform.  Beyond a row by
+// ds_bpermute.
+template <int M>
+HCN_DEV double xshfl(double v) {
+    if constexpr (M <= 8) {
+        constexpr int ctrl = M == 1 ? 0xB1 : M == 2 ? 0x4E : M == 4 ? 0x141 : 0x140;
+        const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+        const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, ctrl, 0xF, 0xF, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), ctrl, 0xF, 0xF, false);
+        return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+    } else {
+        return __shfl_xor(v, M);
+    }
+}
+template <int M>
+HCN_DEV dd xshfl(const dd &v) {
+    return dd{xshfl<M>(v.hi), xshfl<M>(v.lo)};
+}
+template <int M>
+HCN_DEV qd xshfl(const qd &v) {
+    return qd{xshfl<M>(v.c0), xshfl<M>(v.c1), xshfl<M>(v.c2), xshfl<M>(v.c3)};
 }
 
-// sum over the GRP consecutive lanes of a group, lower lane first
-template <class R, int GRP>
+// sum over the GRP consecutive lanes of a group (levels M, 2M, ... < GRP),
+// lower lane first, so every lane of the group holds the same bits
+template <class R, int GRP, int M = 1>
 HCN_DEV R group_sum(R v, int lane) {
-#pragma unroll
-    for (int m = 1; m < GRP; m <<= 1) {
-        const R o = gshfl(v, m);
-        v = (lane & m) ? add(o, v) : add(v, o);
+    if constexpr (M >= GRP) {
+        return v;
+    } else {
+        const R o = xshfl<M>(v);
+        v = (lane & M) ? add(o, v) : add(v, o);
+        return group_sum<R, GRP, 2 * M>(v, lane);
     }
-    return v;
 }
 
-template <class R, int GRP>
+template <class R, int GRP, int M = 1>
 HCN_DEV cx<R> group_csum(cx<R> v, int lane) {
-#pragma unroll
-    for (int m = 1; m < GRP; m <<= 1) {
-        const cx<R> o{gshfl(v.re, m), gshfl(v.im, m)};
-        v = (lane & m) ? cadd(o, v) : cadd(v, o);
+    if constexpr (M >= GRP) {
+        return v;
+    } else {
+        const cx<R> o{xshfl<M>(v.re), xshfl<M>(v.im)};
+        v = (lane & M) ? cadd(o, v) : cadd(v, o);
+        return group_csum<R, GRP, 2 * M>(v, lane);
     }
-    return v;
 }
 
 // bytes of LDS that hold [A | b] of one problem

@@ -45,24 +45,12 @@ HCN_DEV __host__ inline int tiled_rpl(int N, int P) {
 
 template <class R>
 HCN_DEV cx<R> wave_csum(cx<R> v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const cx<R> o{gshfl(v.re, m), gshfl(v.im, m)};
-        v = (lane & m) ? cadd(o, v) : cadd(v, o);
-    }
-    return v;
+    return group_csum<R, 64>(v, threadIdx.x & 63);
 }
 
 template <class R>
 HCN_DEV R wave_rsum(R v) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const R o = gshfl(v, m);
-        v = (lane & m) ? add(o, v) : add(v, o);
-    }
-    return v;
+    return group_sum<R, 64>(v, threadIdx.x & 63);
 }
 
 template <class R, int RPL>

@@ -63,7 +63,7 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_sys_degrees", "hcn_eval_ws_bytes", "hcn_eval_jac", "hcn_mgs_ws_bytes",
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
-           "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_set_chunk_bytes", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
+           "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_set_chunk_bytes", "hcn_set_mon_uniform", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
            "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load", "hcn_autotune",
            "hcn_batch_create", "hcn_batch_destroy", "hcn_batch_device_bytes",
            "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_set_split", "hcn_batch_step",
@@ -104,6 +104,7 @@ def _load():
     lib.hcn_set_mgs_variant.argtypes = [ci]
     lib.hcn_set_mgs_panel.argtypes = [ci]
     lib.hcn_set_chunk_bytes.argtypes = [sz]
+    lib.hcn_set_mon_uniform.argtypes = [ci]
     lib.hcn_newton_mixed_ws_bytes.argtypes = [vp, ci]
     lib.hcn_newton_mixed_ws_bytes.restype = sz
     lib.hcn_newton_mixed.argtypes = lib.hcn_newton.argtypes
@@ -401,6 +402,11 @@ def set_mgs_variant(variant: int) -> None:
 def set_mgs_panel(T: int) -> None:
     """Panel width of the tiled MGS variant (see hcn_set_mgs_panel)."""
     _check(_lib.hcn_set_mgs_panel(int(T)))
+
+
+def set_mon_uniform(on: bool) -> None:
+    """Uniform (1) or branching (0) common factor in the monomial kernels (see hcn_set_mon_uniform)."""
+    _check(_lib.hcn_set_mon_uniform(1 if on else 0))
 
 
 def set_chunk_bytes(nbytes: int) -> None:

@@ -177,6 +177,52 @@ def test_eval_sparse512_sampled(H):
     _check_eval(H, ps, xs)
 
 
+def test_monomials_uniform_form_bitwise(H):
+    """The uniform form of the common factor (same products in every lane,
+    powers tabulated per point) gives bitwise the f and J of the branching
+    form: largest exponent 3 with 16 and with up to 20 variables per
+    monomial (registers and output-slot forward products), largest exponent
+    2, exponents up to 5, the FP64 Jacobian of the mixed-precision step, and
+    a slot-table batch."""
+    import torch
+    P = 2
+    rng = np.random.default_rng(31)
+    cases = [(S.dense32_system(0, P), S.dense32_points(2, 3, P)),
+             (_ragged_system(P), random_points(rng, 3, 24, P)),
+             (S.small_track_system(2, P), random_points(rng, 3, 8, P)),
+             (S.random_system(S.rng_for(3, 901), 12, 12, (3, 8), (1, 6), (1, 2, 3, 4, 5), P),
+              random_points(rng, 3, 12, P))]
+    try:
+        for ps, xs in cases:
+            sysd = H.System(ps)
+            out = {}
+            for uni in (True, False):
+                H.set_mon_uniform(uni)
+                f, J = H.eval_jac(sysd, dev(xs))
+                xd = dev(xs)
+                st, it, nm = H.newton(sysd, xd, mixed=True, max_iter=2)
+                out[uni] = [host(f), host(J), host(xd), host(st), host(nm)]
+            for a, b in zip(out[True], out[False]):
+                assert _bitwise_equal(a, b), ps.name
+            sysd.free()
+        cases_b = _batch_cases(P)
+        systems = {id(c[0]): H.System(c[0]) for c in cases_b}
+        maxs = max(sd.info().nslots for sd in systems.values())
+        res = {}
+        for uni in (True, False):
+            H.set_mon_uniform(uni)
+            bt = H.Batch(P, capacity=len(cases_b), max_n=8, max_nslots=maxs, max_steps=30)
+            for slot, (ps, gam, x0) in enumerate(cases_b):
+                bt.add(slot, systems[id(ps)], gam, dev(x0))
+            bt.run()
+            res[uni] = [bt.result(slot, ps.n) for slot, (ps, _, _) in enumerate(cases_b)]
+            bt.free()
+        for (xa, ra), (xb, rb) in zip(res[True], res[False]):
+            assert _bitwise_equal(host(xa), host(xb)) and ra.tobytes() == rb.tobytes()
+    finally:
+        H.set_mon_uniform(True)
+
+
 def test_eval_batch_independent_and_deterministic(H):
     ps = S.dense32_system(0, 2)
     xs = S.dense32_points(1, 6, 2)

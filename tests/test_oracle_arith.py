@@ -171,3 +171,23 @@ def test_complex_ops(P):
     i[0, 1, 0] = 1.0
     m1 = O.elementwise("cmul", P, i, i)
     assert m1[0, 0, 0] == -1.0 and np.all(m1[0, 0, 1:] == 0) and np.all(m1[0, 1] == 0)
+
+
+def test_products_by_one_and_small_scalings_exact():
+    """DD and FP64 facts the uniform monomial kernel relies on: a complex
+    product by 1 (on either side) returns a normalised operand bit for bit,
+    and the product by the double 1 or 2 equals the operand or its exact
+    double (so scaling by an exponent 1 or 2 through mul_d changes no bit)."""
+    P = 2
+    rng = np.random.default_rng(2024)
+    cnt = 300
+    a = _rand_numbers(rng, P, 2 * cnt).reshape(cnt, 2, P)
+    a[:20] = 0.0                       # zeros and single-limb values too
+    a[20:40, :, 1] = 0.0
+    one = np.zeros((cnt, 2, P))
+    one[:, 0, 0] = 1.0
+    assert np.array_equal(O.elementwise("cmul", P, a, one), a)
+    assert np.array_equal(O.elementwise("cmul", P, one, a), a)
+    re = a[:, 0, :].copy()
+    assert np.array_equal(O.elementwise("mul_d", P, re, np.ones(cnt)), re)
+    assert np.array_equal(O.elementwise("mul_d", P, re, np.full(cnt, 2.0)), 2.0 * re)
