@@ -37,6 +37,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+# HBM traffic per launch of the dense-DD kernels at 10240 points, from
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this leg (KiB per dispatch),
+# calibrated on the 10 MiB copy of the start points in the same runs
+# (FETCH_SIZE reads 5132.5 KiB, WRITE_SIZE 10240 KiB for 10,485,760 bytes);
+# valid for the MGS configuration they were taken with and for the kernels as
+# they are now (summary and commands: profiles/newton_step_dense32_dd_b10240.md)
+HBM_COUNTERS_KIB = {"mgs": (1493298.0, 5416262.0), "eval_monomials": (36559.8, 5570564.0),
+                    "eval_sums": (6102775.6, 339643.5)}
+HBM_COUNTERS_MGS_CONFIG = (8, 0)
+FETCH_CAL, WRITE_CAL = 10485760 / (5132.5 * 1024), 1.0
 _T0 = time.time()
 
 
@@ -399,6 +409,11 @@ def main() -> int:
     avg_ms = dom_ms / max(dom_cnt, 1)
     flops_launch = dd["flops"][dom] * dd["B"]
     achieved = flops_launch / (avg_ms / 1e3) / 1e12
+    traffic = None
+    tuned_cfg = tuple(dd["tuned"][:2]) if dd["tuned"] else (16, 0)
+    if dom in HBM_COUNTERS_KIB and dd["B"] == 10240 and (dom != "mgs" or tuned_cfg == HBM_COUNTERS_MGS_CONFIG):
+        fk, wk = HBM_COUNTERS_KIB[dom]
+        traffic = fk * 1024 * FETCH_CAL + wk * 1024 * WRITE_CAL
     total_tflops = dd["flops"]["total"] * dd["B"] / (ms / 1e3) / 1e12
     qd = r.get("qd")
     single = r.get("single")
@@ -432,7 +447,8 @@ def main() -> int:
             "peak": FP64_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / FP64_PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_unit": "bytes per launch",
             "avg_launch_ms": avg_ms,
             "flops_per_launch": flops_launch,
         },
