@@ -43,9 +43,9 @@ FP64_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 # (FETCH_SIZE reads 5132.5 KiB, WRITE_SIZE 10240 KiB for 10,485,760 bytes);
 # valid for the MGS configuration they were taken with and for the kernels as
 # they are now (summary and commands: profiles/newton_step_dense32_dd_b10240.md)
-HBM_COUNTERS_KIB = {"mgs": (1493298.0, 5416262.0), "eval_monomials": (36559.8, 5570564.0),
-                    "eval_sums": (6102775.6, 339643.5)}
-HBM_COUNTERS_MGS_CONFIG = (8, 0)
+HBM_COUNTERS_KIB = {"mgs": {(8, 0): (1404683.4, 5403123.4), (16, 0): (835265.3, 4592624.3)},
+                    "eval_monomials": (36559.8, 5570564.0), "eval_sums": (6102775.6, 339643.5)}
+MGS_PIN = None  # (lane group, storage) from --mgs-group / --mgs-storage, else autotuned
 FETCH_CAL, WRITE_CAL = 10485760 / (5132.5 * 1024), 1.0
 _T0 = time.time()
 
@@ -114,7 +114,11 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single"))
         sysd = hcn.System(ps)
         x0 = torch.from_numpy(pts).to(dev)
         x = torch.empty_like(x0)
-        tuned = hcn.autotune(sysd, x0, reps=3) if B > 1 else None
+        if B > 1 and MGS_PIN is not None:
+            hcn.tune_set(P, ps.N, MGS_PIN[0], MGS_PIN[1])
+            tuned = (MGS_PIN[0], MGS_PIN[1], None)
+        else:
+            tuned = hcn.autotune(sysd, x0, reps=5) if B > 1 else None
         ws = hcn.newton_ws(sysd, B)
         for _ in range(W):
             x.copy_(x0)
@@ -381,14 +385,21 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--qd-steps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--mgs-group", type=int, default=None,
+                    help="pin the MGS lane-group width (8/16/32) instead of autotuning")
+    ap.add_argument("--mgs-storage", type=int, default=0,
+                    help="with --mgs-group: [A | b] in global memory (0), LDS (1) or registers (2)")
     ap.add_argument("--legs", default="dd,qd,single,sparse512,batch64,serve",
                     help="comma list of dd (the reported line), qd, single; profiling runs use one")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
-              "(paths are independent: a multi-GPU run would shard them, see the design notes)",
+              "(paths are independent: a multi-GPU run would give each GPU its own share of them)",
               file=sys.stderr)
         return 2
+    global MGS_PIN
+    if args.mgs_group is not None:
+        MGS_PIN = (args.mgs_group, args.mgs_storage)
     rank = int(os.environ.get("RANK", "0"))
     cpu = None
     if rank == 0 and not args.no_cpu:
@@ -411,9 +422,11 @@ def main() -> int:
     achieved = flops_launch / (avg_ms / 1e3) / 1e12
     traffic = None
     tuned_cfg = tuple(dd["tuned"][:2]) if dd["tuned"] else (16, 0)
-    if dom in HBM_COUNTERS_KIB and dd["B"] == 10240 and (dom != "mgs" or tuned_cfg == HBM_COUNTERS_MGS_CONFIG):
-        fk, wk = HBM_COUNTERS_KIB[dom]
-        traffic = fk * 1024 * FETCH_CAL + wk * 1024 * WRITE_CAL
+    counters = HBM_COUNTERS_KIB.get(dom)
+    if isinstance(counters, dict):
+        counters = counters.get(tuned_cfg)
+    if counters is not None and dd["B"] == 10240:
+        traffic = counters[0] * 1024 * FETCH_CAL + counters[1] * 1024 * WRITE_CAL
     total_tflops = dd["flops"]["total"] * dd["B"] / (ms / 1e3) / 1e12
     qd = r.get("qd")
     single = r.get("single")

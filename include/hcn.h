@@ -153,13 +153,13 @@ int hcn_set_mgs_variant(int variant);
  * EINVAL outside that range. */
 int hcn_set_mgs_panel(int T);
 
-/* How the monomial kernels form the common factor of R1 in DD and FP64
- * (process-wide; default 1): 1 the same products in every lane of a
- * wavefront (a product by y^0 = 1 where a variable's exponent is 1, powers
- * tabulated per point in LDS, exponent scalings by mul_d, which is exact for
- * exponents 1 and 2), 0 branching on each exponent.  Both give bitwise the
- * same results for normalised inputs; the first avoids running both sides
- * of the branches across a wavefront whose lanes differ in exponents. */
+/* How the monomial kernels form the common factor of R1 (process-wide;
+ * default 1): 1 the same products in every lane of a wavefront (a product by
+ * y^0 = 1 where a variable's exponent is 1, powers tabulated per point in
+ * LDS, exponent scalings by mul_d, which is exact for exponents 1 and 2),
+ * 0 branching on each exponent.  Both give bitwise the same results for
+ * normalised inputs; the first avoids running both sides of the branches
+ * across a wavefront whose lanes differ in exponents. */
 int hcn_set_mon_uniform(int on);
 
 /* Point chunking (process-wide) of hcn_newton_step, hcn_newton,

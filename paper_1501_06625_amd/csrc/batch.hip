@@ -344,7 +344,7 @@ void launch_b_mon(hcn_batch_s *b, hipStream_t s) {
     // its own); the uniform form of the common factor when every system
     // allows it (both forms give the same bits)
     size_t lds = 0;
-    bool uni = !b->views.empty();
+    bool uni = !b->views.empty();  // every registered system allows the uniform form
     for (const SysView &v : b->views) {
         lds = std::max(lds, mon_stage_bytes(v, limbs<R>::P));
         if (!mon_uniform(v, limbs<R>::P)) uni = false;

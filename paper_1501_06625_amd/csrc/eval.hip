@@ -86,13 +86,10 @@ static void mon_kb_u(const MonArgs &a, dim3 grid, size_t lds, hipStream_t stream
 
 template <class R, int KB>
 static void mon_kb(const MonArgs &a, dim3 grid, hipStream_t stream) {
-    if constexpr (limbs<R>::P <= 2) {
-        if (mon_uniform(a.s, limbs<R>::P)) {
-            mon_kb_u<R, KB, true>(a, grid, mon_stage_bytes(a.s, limbs<R>::P), stream);
-            return;
-        }
-    }
-    mon_kb_u<R, KB, false>(a, grid, 0, stream);
+    if (mon_uniform(a.s, limbs<R>::P))
+        mon_kb_u<R, KB, true>(a, grid, mon_stage_bytes(a.s, limbs<R>::P), stream);
+    else
+        mon_kb_u<R, KB, false>(a, grid, 0, stream);
 }
 
 template <class R>

@@ -71,10 +71,10 @@ HCN_DEV __host__ size_t mon_stage_bytes(const SysView &s, int RP) {
 }
 
 // whether the monomial kernels use the uniform form of the common factor:
-// DD or FP64, some exponent above one, and the power table staged if needed
-// (host side: also the process-wide switch mon_uniform_enabled)
+// some exponent above one, and the power table staged if needed (host side:
+// also the process-wide switch mon_uniform_enabled)
 HCN_DEV __host__ bool mon_uniform_fits(const SysView &s, int RP) {
-    return RP <= 2 && s.max_e >= 2 && (s.max_e == 2 || mon_stage_bytes(s, RP) > 0);
+    return s.max_e >= 2 && (s.max_e == 2 || mon_stage_bytes(s, RP) > 0);
 }
 bool mon_uniform_enabled();
 inline bool mon_uniform(const SysView &s, int RP) { return mon_uniform_enabled() && mon_uniform_fits(s, RP); }
@@ -100,17 +100,17 @@ HCN_DEV cx<R> cpow_small(const cx<R> &y, int e) {
 // MON_FSLOT parks them in the output slots of the partials they precede and
 // reads them back in the backward sweep; MON_VALUES forms values only.
 //
-// Uniform form (mon_uniform: DD and FP64, some exponent > 1):
+// Uniform form (mon_uniform: some exponent > 1):
 // exponents differ from lane to lane, so a branch per variable would run
 // both ways for the whole wavefront.  Instead every lane multiplies the
 // common factor by y^{a-1} at every position, with y^0 = 1 (a product by 1
-// is exact for a normalised DD / FP64 number) and y^{a-1} from the staged
+// returns a normalised FP64 / DD / QD number unchanged) and y^{a-1} from the staged
 // table, and scales every partial by a with mul_d (exact for a = 1, 2):
 // the same bits as the branching form, in the same operations for all lanes.
 template <class R, int KB, int MODE, bool UNI = false>
 HCN_DEV void mon_one(const SysView &s, int m, const PointView &pv, double *out) {
     constexpr int W = 2 * limbs<R>::P;
-    constexpr bool uni = UNI && limbs<R>::P <= 2;  // callers: mon_uniform
+    constexpr bool uni = UNI;  // callers: mon_uniform
     const int k = s.mon_k[m];
     const int slot = s.mon_slot[m];
     const int stride = s.mon_stride[m];

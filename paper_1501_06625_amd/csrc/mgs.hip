@@ -49,9 +49,10 @@ static bool launch_reg(const MgsArgs &a, hipStream_t stream) {
 template <class R, int GRP>
 static void launch_grp(const MgsArgs &a, hipStream_t stream) {
     // storage of [A | b]: 0 global memory, 1 LDS (when it fits), 2 registers
-    // (when they fit); all three give the same bits
+    // (when they fit); all three give the same bits.  A few problems (latency
+    // rather than throughput) always go to registers when they fit.
     const int mode = tune_mgs_lds(limbs<R>::P, a.N);
-    if (mode == 2 && launch_reg<R, GRP>(a, stream)) return;
+    if ((mode == 2 || a.B <= 64) && launch_reg<R, GRP>(a, stream)) return;
     const size_t bytes = mgs_lds_bytes(a.N, a.n, limbs<R>::P);
     const int lds = (bytes <= mgs_lds_limit() && mode == 1) ? 1 : 0;
     if (lds)

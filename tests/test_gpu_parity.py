@@ -177,7 +177,8 @@ def test_eval_sparse512_sampled(H):
     _check_eval(H, ps, xs)
 
 
-def test_monomials_uniform_form_bitwise(H):
+@pytest.mark.parametrize("P", [2, 4])
+def test_monomials_uniform_form_bitwise(H, P):
     """The uniform form of the common factor (same products in every lane,
     powers tabulated per point) gives bitwise the f and J of the branching
     form: largest exponent 3 with 16 and with up to 20 variables per
@@ -185,8 +186,7 @@ def test_monomials_uniform_form_bitwise(H):
     2, exponents up to 5, the FP64 Jacobian of the mixed-precision step, and
     a slot-table batch."""
     import torch
-    P = 2
-    rng = np.random.default_rng(31)
+    rng = np.random.default_rng(31 + P)
     cases = [(S.dense32_system(0, P), S.dense32_points(2, 3, P)),
              (_ragged_system(P), random_points(rng, 3, 24, P)),
              (S.small_track_system(2, P), random_points(rng, 3, 8, P)),

@@ -173,21 +173,26 @@ def test_complex_ops(P):
     assert m1[0, 0, 0] == -1.0 and np.all(m1[0, 0, 1:] == 0) and np.all(m1[0, 1] == 0)
 
 
-def test_products_by_one_and_small_scalings_exact():
-    """DD and FP64 facts the uniform monomial kernel relies on: a complex
-    product by 1 (on either side) returns a normalised operand bit for bit,
-    and the product by the double 1 or 2 equals the operand or its exact
-    double (so scaling by an exponent 1 or 2 through mul_d changes no bit)."""
-    P = 2
-    rng = np.random.default_rng(2024)
+@pytest.mark.parametrize("P", [2, 4])
+def test_products_by_one_and_small_scalings_exact(P):
+    """Facts the uniform monomial kernel relies on: a complex product by 1
+    (on either side) returns a normalised operand bit for bit, also a
+    product's result, and the product by the double 1 or 2 equals the operand
+    or its exact double (so scaling by an exponent 1 or 2 through mul_d
+    changes no bit)."""
+    rng = np.random.default_rng(2024 + P)
     cnt = 300
     a = _rand_numbers(rng, P, 2 * cnt).reshape(cnt, 2, P)
     a[:20] = 0.0                       # zeros and single-limb values too
-    a[20:40, :, 1] = 0.0
+    a[20:40, :, 1:] = 0.0
     one = np.zeros((cnt, 2, P))
     one[:, 0, 0] = 1.0
+    a[40:60, :, 2:] = 0.0
     assert np.array_equal(O.elementwise("cmul", P, a, one), a)
     assert np.array_equal(O.elementwise("cmul", P, one, a), a)
+    b = _rand_numbers(rng, P, 2 * cnt).reshape(cnt, 2, P)
+    ab = O.elementwise("cmul", P, a, b)
+    assert np.array_equal(O.elementwise("cmul", P, ab, one), ab)
     re = a[:, 0, :].copy()
     assert np.array_equal(O.elementwise("mul_d", P, re, np.ones(cnt)), re)
     assert np.array_equal(O.elementwise("mul_d", P, re, np.full(cnt, 2.0)), 2.0 * re)
