@@ -5,15 +5,15 @@
 // i < k; the Newton update x += dx with its norm and the Fig. 2 tests that
 // follow it).
 //
-// mgs_wg: right-looking.  Every lane forms r_kk = sqrt(||a_k||^2) and
-// 1/r_kk from the norm in LDS (same bits in every lane) and scales its rows
-// of a_k; then each lane group owns trailing columns j > k (the right-hand
-// side last), forms r_kj = q_k^H a_j over its rows and a butterfly across
-// its GROUP lanes, and updates a_j -= r_kj q_k on its rows; the group that
-// updates column k+1 forms its norm right after (two barriers per column).  Butterflies add
-// the lower lane's value first, so every lane of a group holds bitwise the
-// same sum.  When [A | b] fits in LDS the workgroup copies it there first;
-// the arithmetic is the same either way.
+// mgs_wg: right-looking.  At step k each lane group owns trailing columns
+// j > k (the right-hand side last), forms r_kj = q_k^H a_j over its rows and
+// a butterfly across its GROUP lanes, and updates a_j -= r_kj q_k on its
+// rows; the group that updates column k+1 then forms its norm, r_{k+1,k+1},
+// 1/r_{k+1,k+1} and q_{k+1} on its rows right away (look-ahead), so one
+// barrier per column separates the steps.  Butterflies add the lower lane's
+// value first, so every lane of a group holds bitwise the same sum.  When
+// [A | b] fits in LDS the workgroup copies it there first; the arithmetic is
+// the same either way.
 #pragma once
 
 #include "internal.hpp"
@@ -245,7 +245,6 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
     constexpr int NGRP = MGS_THREADS / GRP;
     extern __shared__ double lds_cols[];
     __shared__ int s_flag;
-    __shared__ double s_norm[4];
     const int tid = threadIdx.x;
     const int g = tid / GRP;
     const int lane = tid % GRP;
@@ -281,35 +280,38 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
         }
         return group_sum<R, GRP>(s, lane);
     };
-    if (tid == 0) s_flag = 0;
-    __syncthreads();
-    if (g == 0) {
-        const R s0 = group0_norm2(col(0));
-        if (lane == 0) rstore(s_norm, s0);
-    }
-    __syncthreads();
-
-    for (int k = 0; k < n; ++k) {
-        double *ak = col(k);
-        // every lane forms r_kk and 1/r_kk from the shared norm (same bits)
-        R s;
-        rload(s_norm, s);
-        const R rkk = sqrt(s);
-        if (!(lead(rkk) > 0.0) || !rfinite(rkk)) {
-            s_flag = 1;
-            break;
-        }
+    // column j, just updated by the calling group: r_jj = sqrt(||a_j||^2),
+    // 1/r_jj and q_j = a_j / r_jj on the group's rows; false when singular
+    auto normalise = [&](int j, double *aj) -> bool {
+        const R rkk = sqrt(group0_norm2(aj));
+        if (!(lead(rkk) > 0.0) || !rfinite(rkk)) return false;
         const R iv = div(rmake<R>(1.0), rkk);
-        if (tid == 0) {
-            rstore(p.inv + (size_t)k * P, iv);
+        if (lane == 0) {
+            rstore(p.inv + (size_t)j * P, iv);
             const cx<R> rc{rkk, rmake<R>(0.0)};
-            cstore(p.R + ((size_t)k * n + k) * W, rc);
+            cstore(p.R + ((size_t)j * n + j) * W, rc);
         }
-        for (int i = tid; i < N; i += MGS_THREADS) {
-            double *q = ak + (size_t)i * W;
+        for (int i = lane; i < N; i += GRP) {
+            double *q = aj + (size_t)i * W;
             cstore(q, cscale(iv, cload<R>(q)));
         }
-        __syncthreads();
+        return true;
+    };
+    // singular column seen, by the parity of the column (written while the
+    // previous step runs, read after its barrier: every thread decides alike)
+    __shared__ int s_bad[2];
+    if (tid < 2) s_bad[tid] = 0;
+    __syncthreads();
+    if (g == 0 && !normalise(0, col(0)) && lane == 0) s_bad[0] = 1;
+    __syncthreads();
+
+    bool singular = false;
+    for (int k = 0; k < n; ++k) {
+        if (s_bad[k & 1]) {
+            singular = true;
+            break;
+        }
+        double *ak = col(k);
         for (int j = k + 1 + g; j <= n; j += NGRP) {
             double *aj = col(j);
             cx<R> r = czero<R>();
@@ -325,16 +327,13 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
                 double *q = aj + (size_t)i * W;
                 cstore(q, csub(cload<R>(q), cmul(r, cload<R>(ak + (size_t)i * W))));
             }
-            // look ahead: the group of column k+1 forms its norm right away
-            if (j == k + 1 && j < n) {
-                const R sn = group0_norm2(aj);
-                if (lane == 0) rstore(s_norm, sn);
-            }
+            // look ahead: the group of column k+1 normalises it right away
+            if (j == k + 1 && j < n && !normalise(j, aj) && lane == 0) s_bad[(k + 1) & 1] = 1;
         }
         __syncthreads();
     }
     // a plain solve returns Q and the projected right-hand side in place
-    if (p.lds && p.mode == MGS_SOLVE && !s_flag) {
+    if (p.lds && p.mode == MGS_SOLVE && !singular) {
         for (size_t q = tid; q < (size_t)(n + 1) * cst; q += MGS_THREADS) {
             const int j = (int)(q / cst);
             const size_t off = q - (size_t)j * cst;
@@ -342,17 +341,16 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
             dst[off] = lds_cols[q];
         }
     }
-    mgs_epilogue<R>(p, s_flag != 0);
+    mgs_epilogue<R>(p, singular);
 }
 
 // Register-resident form of mgs_wg, for problems with N <= GRP * RPL rows and
 // n + 1 <= NGRP * CPG columns.  Column j belongs to lane group j % NGRP (its
 // slot j / NGRP); lane l of the group holds rows l, l + GRP, ... of each of
-// its columns in registers for the whole factorisation.  At step k the owner
-// of column k forms r_kk and 1/r_kk from the norm it computed at step k - 1,
-// scales its column into q_k and writes q_k to LDS; after one barrier every
-// group projects q_k out of its columns j > k, the owner of column k + 1
-// forming that column's norm right after its update.  Each element sees the
+// its columns in registers for the whole factorisation.  At step k every
+// group projects q_k (read from LDS) out of its columns j > k; the owner of
+// column k + 1 then forms its norm, r, 1/r and q_{k+1}, which it writes to the
+// other of two LDS buffers; one barrier per column.  Each element sees the
 // same operations as in mgs_wg and every reduction runs over the same rows in
 // the same order with the same butterfly, so the results are bitwise those of
 // mgs_wg; [A | b] is read once and only R (and Q for a plain solve) written.
@@ -392,39 +390,39 @@ HCN_DEV void mgs_reg(const MgsProblem &p) {
             if (lane + r * GRP < N) t = r == 0 ? cnorm2(u[r]) : add(t, cnorm2(u[r]));
         return group_sum<R, GRP>(t, lane);
     };
-    R pend = rmake<R>(0.0);  // the norm of this group's next column
-    if (g == 0) pend = norm2(v[0]);
-    if (tid == 0) s_flag = 0;
+    // column j in slot c of the calling group, just updated: r_jj, 1/r_jj
+    // and q_j into the registers and into the LDS buffer q; false when singular
+    auto normalise = [&](int j, cx<R>(&u)[RPL], double *q) -> bool {
+        const R rkk = sqrt(norm2(u));
+        if (!(lead(rkk) > 0.0) || !rfinite(rkk)) return false;
+        const R iv = div(rmake<R>(1.0), rkk);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            u[r] = cscale(iv, u[r]);
+            cstore(q + (size_t)(lane + r * GRP) * W, u[r]);
+        }
+        if (lane == 0) {
+            rstore(p.inv + (size_t)j * P, iv);
+            const cx<R> rc{rkk, rmake<R>(0.0)};
+            cstore(p.R + ((size_t)j * n + j) * W, rc);
+        }
+        return true;
+    };
+    // singular column seen, by the parity of the column (written while the
+    // previous step runs, read after its barrier: every thread decides alike)
+    __shared__ int s_bad[2];
+    if (tid < 2) s_bad[tid] = 0;
+    __syncthreads();
+    if (g == 0 && !normalise(0, v[0], s_q[0]) && lane == 0) s_bad[0] = 1;
     __syncthreads();
 
+    bool singular = false;
     for (int k = 0; k < n; ++k) {
-        double *q = s_q[k & 1];
-        if (g == k % NGRP) {
-            const int kc = k / NGRP;
-            const R rkk = sqrt(pend);
-            const bool bad = !(lead(rkk) > 0.0) || !rfinite(rkk);
-            if (!bad) {
-                const R iv = div(rmake<R>(1.0), rkk);
-#pragma unroll
-                for (int c = 0; c < CPG; ++c) {
-                    if (c != kc) continue;
-#pragma unroll
-                    for (int r = 0; r < RPL; ++r) {
-                        v[c][r] = cscale(iv, v[c][r]);
-                        cstore(q + (size_t)(lane + r * GRP) * W, v[c][r]);
-                    }
-                }
-                if (lane == 0) {
-                    rstore(p.inv + (size_t)k * P, iv);
-                    const cx<R> rc{rkk, rmake<R>(0.0)};
-                    cstore(p.R + ((size_t)k * n + k) * W, rc);
-                }
-            } else if (lane == 0) {
-                s_flag = 1;
-            }
+        if (s_bad[k & 1]) {
+            singular = true;
+            break;
         }
-        __syncthreads();
-        if (s_flag) break;
+        const double *q = s_q[k & 1];
 #pragma unroll
         for (int c = 0; c < CPG; ++c) {
             const int j = g + c * NGRP;
@@ -443,11 +441,15 @@ HCN_DEV void mgs_reg(const MgsProblem &p) {
             for (int r = 0; r < RPL; ++r)
                 if (lane + r * GRP < N)
                     v[c][r] = csub(v[c][r], cmul(acc, cload<R>(q + (size_t)(lane + r * GRP) * W)));
-            if (j == k + 1 && j < n) pend = norm2(v[c]);
+            // look ahead: the owner of column k+1 normalises it into the
+            // other LDS buffer right away
+            if (j == k + 1 && j < n && !normalise(j, v[c], s_q[(k + 1) & 1]) && lane == 0)
+                s_bad[(k + 1) & 1] = 1;
         }
+        __syncthreads();
     }
     // a plain solve returns Q and the projected right-hand side in place
-    if (p.mode == MGS_SOLVE && !s_flag) {
+    if (p.mode == MGS_SOLVE && !singular) {
 #pragma unroll
         for (int c = 0; c < CPG; ++c) {
             const int j = g + c * NGRP;
@@ -460,7 +462,7 @@ HCN_DEV void mgs_reg(const MgsProblem &p) {
         }
     }
     __syncthreads();
-    mgs_epilogue<R>(p, s_flag != 0);
+    mgs_epilogue<R>(p, singular);
 }
 
 // rows per lane and columns per group of mgs_reg for a problem (0 when it
