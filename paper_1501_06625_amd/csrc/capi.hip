@@ -261,6 +261,29 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
                 }
             }
     }
+    // the same lists interleaved per wavefront of 64 consecutive entries
+    // (entry c of entry e at J_wbase[e / 64] + 64 c + e % 64), so that the
+    // lanes of a wavefront read their c-th slot indices from one cache line;
+    // dropped when the padding to each wavefront's longest list would cost
+    // more than four times the lists
+    const long nwv = (nJ + 63) / 64;
+    std::vector<int32_t> J_wbase(nwv + 1, 0), J_ilv;
+    {
+        long total = 0;
+        for (long w = 0; w < nwv; ++w) {
+            int mx = 0;
+            for (long e = w * 64; e < std::min(nJ, (w + 1) * 64); ++e) mx = std::max(mx, J_ptr[e + 1] - J_ptr[e]);
+            total += 64L * mx;
+            if (total > (1L << 30)) break;
+            J_wbase[w + 1] = (int32_t)total;
+        }
+        if (total <= 4L * std::max(npairs, 1) + 4096) {
+            J_ilv.assign(std::max<long>(total, 1), 0);
+            for (long e = 0; e < nJ; ++e)
+                for (int c = 0; c < J_ptr[e + 1] - J_ptr[e]; ++c)
+                    J_ilv[J_wbase[e / 64] + 64L * c + e % 64] = J_list[J_ptr[e] + c];
+        }
+    }
     std::vector<int32_t> deg(N, 0);
     for (int i = 0; i < N; ++i)
         for (int m = eq_ptr[i]; m < eq_ptr[i + 1]; ++m) {
@@ -281,6 +304,8 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
     c.take<int32_t>(f_list.size());
     c.take<int32_t>(J_ptr.size());
     c.take<int32_t>(J_list.size());
+    c.take<int32_t>(J_wbase.size());
+    c.take<int32_t>(std::max<size_t>(J_ilv.size(), 1));
     c.take<int32_t>(deg.size());
     const size_t bytes = c.off;
     void *dmem = nullptr;
@@ -300,6 +325,8 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
     auto *d_flist = d.take<int32_t>(f_list.size());
     auto *d_Jptr = d.take<int32_t>(J_ptr.size());
     auto *d_Jlist = d.take<int32_t>(J_list.size());
+    auto *d_Jwbase = d.take<int32_t>(J_wbase.size());
+    auto *d_Jilv = d.take<int32_t>(std::max<size_t>(J_ilv.size(), 1));
     auto *d_deg = d.take<int32_t>(deg.size());
     hipError_t e = hipSuccess;
     e = e ? e : up(d_k, h_k);
@@ -312,6 +339,8 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
     e = e ? e : up(d_flist, f_list);
     e = e ? e : up(d_Jptr, J_ptr);
     e = e ? e : up(d_Jlist, J_list);
+    e = e ? e : up(d_Jwbase, J_wbase);
+    if (!J_ilv.empty()) e = e ? e : up(d_Jilv, J_ilv);
     e = e ? e : up(d_deg, deg);
     if (e != hipSuccess) {
         (void)hipFree(dmem);
@@ -341,6 +370,8 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
     v.f_list = d_flist;
     v.J_ptr = d_Jptr;
     v.J_list = d_Jlist;
+    v.J_wbase = d_Jwbase;
+    v.J_ilv = J_ilv.empty() ? nullptr : d_Jilv;
     v.deg = d_deg;
     *out = sys;
     return HCN_OK;

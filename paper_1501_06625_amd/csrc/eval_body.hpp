@@ -224,8 +224,21 @@ HCN_DEV double sum_one(const SysView &s, long e, const double *sc, const double 
     const bool isJ = e < nJ;
     const int k = isJ ? (int)(e / s.N) : -1;
     const int i = isJ ? (int)(e % s.N) : (int)(e - nJ);
-    cx<R> acc = isJ ? sum_list<R>(sc, s.J_list, s.J_ptr[e], s.J_ptr[e + 1])
-                    : sum_list<R>(sc, s.f_list, s.f_ptr[i], s.f_ptr[i + 1]);
+    cx<R> acc;
+    if (isJ && s.J_ilv) {
+        // the interleaved copy of the list: lanes of a wavefront read their
+        // c-th indices from consecutive words
+        const int32_t *li = s.J_ilv + s.J_wbase[e >> 6] + (e & 63);
+        const int len = s.J_ptr[e + 1] - s.J_ptr[e];
+        acc = czero<R>();
+        for (int c = 0; c < len; ++c) {
+            const cx<R> v = cload<R>(sc + (size_t)li[64 * c] * W);
+            acc = c == 0 ? v : cadd(acc, v);
+        }
+    } else {
+        acc = isJ ? sum_list<R>(sc, s.J_list, s.J_ptr[e], s.J_ptr[e + 1])
+                  : sum_list<R>(sc, s.f_list, s.f_ptr[i], s.f_ptr[i + 1]);
+    }
     if (hom_on) {
         // s_f = t^k, s_g = gamma (1-t)^k (1-t formed exactly)
         const R tt = rmake<R>(t);
