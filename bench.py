@@ -290,6 +290,15 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
     fl_plain = [flops.newton_step(ps, 2) for ps in systems]
     fl_mixed = [flops.mixed_step(ps, 2) for ps in systems]
     res = {"systems": nsys, "paths": nsys * per, "timed_steps": steps}
+    # tune the MGS for every row-count bucket (a power of two) on one system
+    # of the bucket at 256 of its start points; the batch reads the same table
+    progress("batch: tuning the MGS per row-count bucket")
+    tuned = {}
+    for ps, sd, st in zip(systems, loaded, starts):
+        bucket = 1 << max(3, (ps.N - 1).bit_length())
+        if bucket not in tuned:
+            tuned[bucket] = hcn.autotune(sd, st.repeat(4, 1, 1, 1).contiguous(), reps=3)[:2]
+    res["mgs_tuned"] = {str(k): list(v) for k, v in sorted(tuned.items())}
     progress("batch: systems and start points ready")
     for mode in ("plain", "mixed"):
         progress(f"batch: {mode}")

@@ -176,14 +176,19 @@ int hcn_set_chunk_bytes(size_t bytes);
  * (8, 16 or 32 lanes per column) and the storage of [A | b] during the
  * factorisation, mgs_lds: 0 global memory, 1 staged in LDS (when it fits in
  * 80 KB), 2 held in the registers of the lane groups that own the columns
- * (when N <= group * 4 and the columns fit; the slot-table batch treats 2 as
- * 0), per precision P (1 = the FP64 solve of the mixed-precision step, 2, 4)
- * and row count N (bucketed to the next power of two >= 8).  Defaults: 16,
- * global memory.  Every choice gives bitwise the same results, and it depends
+ * (when N <= group * 4 and the columns fit), 3 in registers one panel of
+ * columns at a time, left-looking (Section 1: each q column is read once per
+ * later panel instead of the trailing matrix at every step; DD and FP64,
+ * when N <= group * 16); the slot-table batch treats 2 as 0.
+ * Problems of batches of at most 64 use 2 when it fits.  Per precision P
+ * (1 = the FP64 solve of the mixed-precision step, 2, 4)
+ * and row count N (bucketed to the next power of two >= 8).  Defaults: 16
+ * lanes; storage 3 for DD and FP64 with 32 < N <= 256, else global memory.
+ * Every choice gives bitwise the same results, and it depends
  * only on (P, N), so a problem's result does not depend on the batch it is
  * solved in.  save/load: text, one "P N group lds" line per entry.
  * hcn_autotune (batch section) fills the table by timing.  EINVAL for a
- * group other than 8/16/32 or mgs_lds outside 0..2. */
+ * group other than 8/16/32 or mgs_lds outside 0..3. */
 int hcn_tune_set(int P, int N, int mgs_group, int mgs_lds);
 int hcn_tune_get(int P, int N, int *mgs_group, int *mgs_lds);
 int hcn_tune_save(const char *path);

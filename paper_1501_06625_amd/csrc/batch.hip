@@ -194,6 +194,13 @@ __global__ __launch_bounds__(MGS_THREADS) void k_b_mgs(BatchDev d, const int *sl
     mgs_wg<R, GRP>(slot_problem<R>(d, slots[blockIdx.x]));
 }
 
+// left-looking panel MGS (bitwise that of k_b_mgs) for slots whose table
+// entry asks for it; RPL covers the largest row count of the launch
+template <class R, int GRP, int RPL>
+__global__ __launch_bounds__(MGS_THREADS) void k_b_mgs_panel(BatchDev d, const int *slots) {
+    mgs_panel<R, GRP, RPL>(slot_problem<R>(d, slots[blockIdx.x]));
+}
+
 // tiled MGS of the large slots: the Fig. 2 tests before the solve (already
 // taken by the residual pass in mixed mode) and a cleared singular flag
 __global__ void k_bt_pre(BatchDev d, const int *slots, int count) {
@@ -276,6 +283,11 @@ int bfail(int code, const char *msg) {
 
 size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// one-workgroup MGS forms per lane-group width: k_b_mgs, and k_b_mgs_panel
+// with 1, 2, 4, 8 or 16 rows per lane
+constexpr int NFORM = 6;
+constexpr int NMGS_GROUPS = 3 * NFORM;
+
 int kbucket_b(int k) {
     if (k <= 4) return 4;
     if (k <= 8) return 8;
@@ -307,8 +319,10 @@ struct hcn_batch_s {
     int split_n = 0;
     int *d_big = nullptr;
     int n_big = 0, big_maxn = 0, big_maxN = 0;
-    int grp_off[3] = {0, 0, 0}, grp_cnt[3] = {0, 0, 0};
-    size_t grp_lds[3] = {0, 0, 0};
+    // one-workgroup MGS launches: lane-group width index g (8, 16, 32) times
+    // form f (0: k_b_mgs, 1 + log2 RPL: k_b_mgs_panel), group g * NFORM + f
+    int grp_off[NMGS_GROUPS] = {}, grp_cnt[NMGS_GROUPS] = {};
+    size_t grp_lds[NMGS_GROUPS] = {};
     long mon_cap = 0, sum_cap = 0;
     int32_t *d_done = nullptr, *d_running = nullptr;
     int32_t *h_running = nullptr, *h_done = nullptr;
@@ -383,21 +397,37 @@ void launch_b_tiled(hcn_batch_s *b, hipStream_t s) {
     hipLaunchKernelGGL(k_bt_finish<R>, dim3(b->n_big), dim3(MGS_THREADS), 0, s, b->d, b->d_big);
 }
 
+template <class R, int GRP>
+void launch_b_mgs_grp(hcn_batch_s *b, int g, hipStream_t s) {
+    const BatchDev &d = b->d;
+    for (int f = 0; f < NFORM; ++f) {
+        const int q = g * NFORM + f;
+        const int cnt = b->grp_cnt[q];
+        if (cnt == 0) continue;
+        const int *list = b->d_slots + b->grp_off[q];
+        const dim3 grid(cnt), block(MGS_THREADS);
+        if (f == 0) {
+            hipLaunchKernelGGL((k_b_mgs<R, GRP>), grid, block, b->grp_lds[q], s, d, list);
+            continue;
+        }
+        if constexpr (limbs<R>::P != 4) {
+            switch (f) {
+                case 1: hipLaunchKernelGGL((k_b_mgs_panel<R, GRP, 1>), grid, block, 0, s, d, list); break;
+                case 2: hipLaunchKernelGGL((k_b_mgs_panel<R, GRP, 2>), grid, block, 0, s, d, list); break;
+                case 3: hipLaunchKernelGGL((k_b_mgs_panel<R, GRP, 4>), grid, block, 0, s, d, list); break;
+                case 4: hipLaunchKernelGGL((k_b_mgs_panel<R, GRP, 8>), grid, block, 0, s, d, list); break;
+                default: hipLaunchKernelGGL((k_b_mgs_panel<R, GRP, 16>), grid, block, 0, s, d, list); break;
+            }
+        }
+    }
+}
+
 template <class R>
 void launch_b_mgs(hcn_batch_s *b, hipStream_t s) {
     launch_b_tiled<R>(b, s);
-    const BatchDev &d = b->d;
-    const int grps[3] = {8, 16, 32};
-    for (int g = 0; g < 3; ++g) {
-        if (b->grp_cnt[g] == 0) continue;
-        const int *list = b->d_slots + b->grp_off[g];
-        const size_t lds = b->grp_lds[g];
-        switch (grps[g]) {
-            case 8: hipLaunchKernelGGL((k_b_mgs<R, 8>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
-            case 16: hipLaunchKernelGGL((k_b_mgs<R, 16>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
-            default: hipLaunchKernelGGL((k_b_mgs<R, 32>), dim3(b->grp_cnt[g]), dim3(MGS_THREADS), lds, s, d, list); break;
-        }
-    }
+    launch_b_mgs_grp<R, 8>(b, 0, s);
+    launch_b_mgs_grp<R, 16>(b, 1, s);
+    launch_b_mgs_grp<R, 32>(b, 2, s);
 }
 
 template <class R>
@@ -447,11 +477,10 @@ bool big_slot(const hcn_batch_s *b, const SysView &v) {
 // work lists from the occupied slots; slots grouped by MGS lane-group width
 int rebuild(hcn_batch_s *b) {
     std::vector<int2> mon, sum, sumf;
-    std::vector<int> lists[3], big;
+    std::vector<int> lists[NMGS_GROUPS], big;
     const int Ps = b->d.mixed ? 1 : b->P;  // precision of the solve
     b->big_maxn = b->big_maxN = 0;
-    const int grps[3] = {8, 16, 32};
-    size_t lds_need[3] = {0, 0, 0};
+    size_t lds_need[NMGS_GROUPS] = {};
     for (int s = 0; s < b->cap; ++s) {
         if (b->slot_sys[s] < 0) continue;
         const SysView &v = b->views[b->slot_sys[s]];
@@ -468,17 +497,23 @@ int rebuild(hcn_batch_s *b) {
             b->big_maxN = std::max(b->big_maxN, v.N);
             continue;
         }
-        const int grp = tune_mgs_group(Ps, v.N);
+        const int grp = tune_mgs_group(Ps, v.N), choice = tune_mgs_lds(Ps, v.N);
         const int g = grp == 8 ? 0 : grp == 32 ? 2 : 1;
-        lists[g].push_back(s);
+        const int prpl = choice == 3 ? mgs_panel_rpl(v.N, Ps, grp) : 0;
+        if (prpl > 0) {
+            int f = 1;
+            while ((1 << (f - 1)) < prpl) ++f;
+            lists[g * NFORM + f].push_back(s);
+            continue;
+        }
+        lists[g * NFORM].push_back(s);
         const size_t bytes = mgs_lds_bytes(v.N, v.n, Ps);
-        const int lds = (bytes <= mgs_lds_limit() && tune_mgs_lds(Ps, v.N) == 1) ? 1 : 0;
+        const int lds = (bytes <= mgs_lds_limit() && choice == 1) ? 1 : 0;
         b->slot_lds[s] = lds;
-        if (lds) lds_need[g] = std::max(lds_need[g], bytes);
-        (void)grps;
+        if (lds) lds_need[g * NFORM] = std::max(lds_need[g * NFORM], bytes);
     }
     std::vector<int> slots;
-    for (int g = 0; g < 3; ++g) {
+    for (int g = 0; g < NMGS_GROUPS; ++g) {
         b->grp_off[g] = (int)slots.size();
         b->grp_cnt[g] = (int)lists[g].size();
         b->grp_lds[g] = lds_need[g];

@@ -46,13 +46,36 @@ static bool launch_reg(const MgsArgs &a, hipStream_t stream) {
     return false;
 }
 
+template <class R, int GRP, int RPL>
+__global__ __launch_bounds__(MGS_THREADS) void k_mgs_panel(MgsArgs a) {
+    mgs_panel<R, GRP, RPL>(problem_of(a, blockIdx.x));
+}
+
+template <class R, int GRP>
+static bool launch_panel(const MgsArgs &a, hipStream_t stream) {
+    if constexpr (limbs<R>::P != 4) {
+        const dim3 grid(a.B), block(MGS_THREADS);
+        switch (mgs_panel_rpl(a.N, limbs<R>::P, GRP)) {
+            case 1: hipLaunchKernelGGL((k_mgs_panel<R, GRP, 1>), grid, block, 0, stream, a); return true;
+            case 2: hipLaunchKernelGGL((k_mgs_panel<R, GRP, 2>), grid, block, 0, stream, a); return true;
+            case 4: hipLaunchKernelGGL((k_mgs_panel<R, GRP, 4>), grid, block, 0, stream, a); return true;
+            case 8: hipLaunchKernelGGL((k_mgs_panel<R, GRP, 8>), grid, block, 0, stream, a); return true;
+            case 16: hipLaunchKernelGGL((k_mgs_panel<R, GRP, 16>), grid, block, 0, stream, a); return true;
+            default: break;
+        }
+    }
+    return false;
+}
+
 template <class R, int GRP>
 static void launch_grp(const MgsArgs &a, hipStream_t stream) {
     // storage of [A | b]: 0 global memory, 1 LDS (when it fits), 2 registers
-    // (when they fit); all three give the same bits.  A few problems (latency
+    // (when they fit), 3 registers a panel of columns at a time (left-looking,
+    // when a column fits); all give the same bits.  A few problems (latency
     // rather than throughput) always go to registers when they fit.
     const int mode = tune_mgs_lds(limbs<R>::P, a.N);
     if ((mode == 2 || a.B <= 64) && launch_reg<R, GRP>(a, stream)) return;
+    if (mode == 3 && launch_panel<R, GRP>(a, stream)) return;
     const size_t bytes = mgs_lds_bytes(a.N, a.n, limbs<R>::P);
     const int lds = (bytes <= mgs_lds_limit() && mode == 1) ? 1 : 0;
     if (lds)

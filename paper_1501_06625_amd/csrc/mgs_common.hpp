@@ -465,6 +465,132 @@ HCN_DEV void mgs_reg(const MgsProblem &p) {
     mgs_epilogue<R>(p, singular);
 }
 
+// Left-looking by panels, one workgroup per problem (Section 1: left-looking
+// tiles cut the memory traffic of the right-looking form): the workgroup
+// takes the columns NGRP at a time, lane group g holding column j0 + g of the
+// panel in registers (lane l: rows l, l + GRP, ...).  The panel first
+// receives the projections of every earlier column k < j0, in order, with
+// q_k read from memory (final since its own panel); then the panel is
+// factored as in mgs_reg (the owner of column k normalises it into LDS and
+// memory, one barrier per column).  Every column sees the projections
+// k = 0, 1, ... in the same order, over the same rows with the same
+// butterflies, as in mgs_wg, so the results are bitwise those of mgs_wg;
+// [A | b] is read once and each q column once per later panel, instead of
+// the whole trailing matrix at every column step.
+template <class R, int GRP, int RPL>
+HCN_DEV void mgs_panel(const MgsProblem &p) {
+    constexpr int P = limbs<R>::P;
+    constexpr int W = 2 * P;
+    constexpr int NGRP = MGS_THREADS / GRP;
+    __shared__ double s_q[2][GRP * RPL * W];
+    __shared__ int s_flag;
+    __shared__ int s_bad[2];
+    const int tid = threadIdx.x;
+    const int g = tid / GRP;
+    const int lane = tid % GRP;
+    const int N = p.N, n = p.n;
+
+    if (p.mode == MGS_NEWTON_FIG2 || p.mode == MGS_MIXED_SOLVE) {
+        if (tid == 0) s_flag = p.mode == MGS_NEWTON_FIG2 ? fig2_decide(p) : !p.st->c_active;
+        __syncthreads();
+        if (s_flag) return;
+    }
+    auto col = [&](int j) -> double * { return j < n ? p.A + (size_t)j * p.A_cstride : p.bcol; };
+    auto norm2 = [&](const cx<R>(&u)[RPL]) -> R {
+        R t = rmake<R>(0.0);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r)
+            if (lane + r * GRP < N) t = r == 0 ? cnorm2(u[r]) : add(t, cnorm2(u[r]));
+        return group_sum<R, GRP>(t, lane);
+    };
+    // q_k^H u over the lane's rows and the group butterfly, then u -= r q_k
+    auto project = [&](const double *q, cx<R>(&u)[RPL], int j, int k) {
+        cx<R> acc = czero<R>();
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            if (lane + r * GRP < N) {
+                const cx<R> t = cmul_conj(cload<R>(q + (size_t)(lane + r * GRP) * W), u[r]);
+                acc = r == 0 ? t : cadd(acc, t);
+            }
+        }
+        acc = group_csum<R, GRP>(acc, lane);
+        if (lane == 0) cstore(p.R + ((size_t)j * n + k) * W, acc);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r)
+            if (lane + r * GRP < N) u[r] = csub(u[r], cmul(acc, cload<R>(q + (size_t)(lane + r * GRP) * W)));
+    };
+    // column j of the calling group, fully projected: r_jj, 1/r_jj and q_j
+    // into the registers, the LDS buffer q and memory; false when singular
+    auto normalise = [&](int j, cx<R>(&u)[RPL], double *q) -> bool {
+        const R rkk = sqrt(norm2(u));
+        if (!(lead(rkk) > 0.0) || !rfinite(rkk)) return false;
+        const R iv = div(rmake<R>(1.0), rkk);
+        double *aj = col(j);
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            u[r] = cscale(iv, u[r]);
+            cstore(q + (size_t)(lane + r * GRP) * W, u[r]);
+            if (lane + r * GRP < N) cstore(aj + (size_t)(lane + r * GRP) * W, u[r]);
+        }
+        if (lane == 0) {
+            rstore(p.inv + (size_t)j * P, iv);
+            const cx<R> rc{rkk, rmake<R>(0.0)};
+            cstore(p.R + ((size_t)j * n + j) * W, rc);
+        }
+        return true;
+    };
+    if (tid < 2) s_bad[tid] = 0;
+    __syncthreads();
+    bool singular = false;
+    for (int j0 = 0; j0 <= n && !singular; j0 += NGRP) {
+        const int j = j0 + g;
+        const bool own = j <= n;
+        cx<R> v[RPL];
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) {
+            const int i = lane + r * GRP;
+            v[r] = (own && i < N) ? cload<R>(col(j) + (size_t)i * W) : czero<R>();
+        }
+        // the projections of the earlier panels' columns, in order
+        if (own)
+            for (int k = 0; k < j0; ++k) project(col(k), v, j, k);
+        // the panel itself
+        const int k1 = j0 + NGRP < n ? j0 + NGRP : n;
+        if (own && j == j0 && j0 < n && !normalise(j, v, s_q[j0 & 1]) && lane == 0) s_bad[j0 & 1] = 1;
+        __syncthreads();
+        for (int k = j0; k < k1; ++k) {
+            if (s_bad[k & 1]) {
+                singular = true;
+                break;
+            }
+            if (own && j > k) {
+                project(s_q[k & 1], v, j, k);
+                if (j == k + 1 && j < n && !normalise(j, v, s_q[(k + 1) & 1]) && lane == 0)
+                    s_bad[(k + 1) & 1] = 1;
+            }
+            __syncthreads();
+        }
+        // a plain solve returns the projected right-hand side in place
+        if (!singular && own && j == n && p.mode == MGS_SOLVE) {
+#pragma unroll
+            for (int r = 0; r < RPL; ++r)
+                if (lane + r * GRP < N) cstore(col(n) + (size_t)(lane + r * GRP) * W, v[r]);
+        }
+    }
+    __syncthreads();
+    mgs_epilogue<R>(p, singular);
+}
+
+// rows per lane of mgs_panel (0 when a column does not fit the register
+// budget of 16 rows per lane, and for QD, whose columns spill to the stack)
+HCN_DEV __host__ inline int mgs_panel_rpl(int N, int P, int grp) {
+    if (P == 4) return 0;
+    const int need = (N + grp - 1) / grp;
+    int r = 1;
+    while (r < need) r <<= 1;
+    return r <= 16 ? r : 0;
+}
+
 // rows per lane and columns per group of mgs_reg for a problem (0 when it
 // does not fit the register budget: at most 8 complex numbers per lane in
 // DD and FP64; in QD at most 4 and one column per group)

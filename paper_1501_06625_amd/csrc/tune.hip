@@ -2,8 +2,9 @@
 //
 // Choices: the lane-group width of the one-workgroup MGS (8, 16 or 32 lanes
 // per column) and where [A | b] lives during the factorisation (0 global
-// memory, 1 staged in LDS, 2 held in registers by the owning lane groups),
-// per precision and row count bucket.  hcn_autotune times a Newton step of a given system for every
+// memory, 1 staged in LDS, 2 held in registers by the owning lane groups,
+// 3 in registers a panel of columns at a time, left-looking), per precision
+// and row count bucket.  hcn_autotune times a Newton step of a given system for every
 // choice (HIP events on the caller's stream) and keeps the fastest; the
 // table can be saved to and loaded from a text file (one line per entry:
 // "P Nbucket group lds").  A choice depends only on (P, N), never on what
@@ -33,10 +34,19 @@ int nbucket(int N) {
     return b;
 }
 
+// untuned: 16 lanes per column; beyond 32 rows (DD and FP64, while a
+// column fits 16 rows per lane) the left-looking panel form, which reads
+// [A | b] once instead of the trailing matrix at every column step
+Choice default_choice(int P, int N) {
+    Choice c;
+    if (P != 4 && N > 32 && N <= 256 && mgs_panel_rpl(N, P, 16) > 0) c.lds = 3;
+    return c;
+}
+
 Choice lookup(int P, int N) {
     std::lock_guard<std::mutex> lk(g_mu);
     auto it = g_table.find({P, nbucket(N)});
-    return it == g_table.end() ? Choice{} : it->second;
+    return it == g_table.end() ? default_choice(P, N) : it->second;
 }
 }  // namespace
 
@@ -59,7 +69,7 @@ extern "C" {
 
 int hcn_tune_set(int P, int N, int mgs_group, int mgs_lds) {
     if ((P != 1 && P != 2 && P != 4) || N < 1 ||
-        (mgs_group != 8 && mgs_group != 16 && mgs_group != 32) || mgs_lds < 0 || mgs_lds > 2)
+        (mgs_group != 8 && mgs_group != 16 && mgs_group != 32) || mgs_lds < 0 || mgs_lds > 3)
         return HCN_EINVAL;
     tune_set(P, N, mgs_group, mgs_lds);
     return HCN_OK;
@@ -133,8 +143,10 @@ int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_gr
     for (int grp : {8, 16, 32}) {
         int rpl = 0, cpg = 0;
         mgs_reg_shape(N, n, P, grp, &rpl, &cpg);
-        for (int lds = 0; lds <= 2; ++lds) {
-            if ((lds == 1 && !lds_fits) || (lds == 2 && rpl == 0)) continue;
+        for (int lds = 0; lds <= 3; ++lds) {
+            if ((lds == 1 && !lds_fits) || (lds == 2 && rpl == 0) ||
+                (lds == 3 && mgs_panel_rpl(N, P, grp) == 0))
+                continue;
             tune_set(P, N, grp, lds);
             float ms = 0.0f;
             for (int pass = 0; pass < 2 && rc == HCN_OK; ++pass) {  // warm-up, then timed

@@ -5,9 +5,10 @@ Bars: elementwise DD/QD operations bit for bit; reductions (f, J) within
 by normwise backward error <= 1e-28 / 1e-58 and forward difference to the
 oracle <= max(1e-28, 16 n kappa u); Newton and tracking decisions equal.
 """
-import mpmath
+import contextlib
 import time
 
+import mpmath
 import numpy as np
 import pytest
 
@@ -606,6 +607,17 @@ def test_mixed_newton_fig2_branches(H):
 # kernel variants from the tuning table
 # ---------------------------------------------------------------------------
 
+@contextlib.contextmanager
+def _tune_restored(H, P, *Ns):
+    """Restore the table entries of (P, N) for every N on exit."""
+    saved = [(N, H.tune_get(P, N)) for N in Ns]
+    try:
+        yield
+    finally:
+        for N, (g, l) in saved:
+            H.tune_set(P, N, g, l)
+
+
 @pytest.mark.parametrize("P", [2, 4])
 def test_tuned_variants(H, P):
     """LDS staging and register residency do not change a bit; other
@@ -614,7 +626,7 @@ def test_tuned_variants(H, P):
     xs = S.dense32_points(3, 2, P)
     sysd = H.System(ps)
     out = {}
-    try:
+    with _tune_restored(H, P, ps.N):
         for grp in (8, 16, 32):
             for lds in (0, 1, 2):
                 H.tune_set(P, ps.N, grp, lds)
@@ -622,8 +634,6 @@ def test_tuned_variants(H, P):
                 _, status = H.newton_step(sysd, xd)
                 assert np.all(host(status) == 0)
                 out[(grp, lds)] = host(xd)
-    finally:
-        H.tune_set(P, ps.N, 16, 0)
     for grp in (8, 16, 32):
         assert _bitwise_equal(out[(grp, 0)], out[(grp, 1)])
         assert _bitwise_equal(out[(grp, 0)], out[(grp, 2)])
@@ -673,32 +683,32 @@ def test_point_chunking_bitwise(H):
 
 
 @pytest.mark.parametrize("P,N,n", [(2, 24, 24), (2, 32, 31), (2, 40, 24), (2, 64, 40), (2, 7, 5),
-                                   (4, 24, 24), (4, 32, 20), (4, 9, 9)])
+                                   (2, 97, 96), (2, 130, 100), (4, 24, 24), (4, 32, 20), (4, 9, 9)])
 def test_mgs_register_storage_bitwise(H, P, N, n):
-    """[A | b] held in registers gives bitwise the Q, R, projected b and dx of
-    the global-memory form, for every lane-group width where it fits (ragged
-    rows and columns, least squares), on three problems at once; a problem
-    with a zero column stays singular."""
+    """[A | b] held in registers (all columns, or a panel at a time,
+    left-looking) gives bitwise the Q, R, projected b and dx of the
+    global-memory form, for every lane-group width where it fits (ragged
+    rows and columns, least squares, several panels), on three problems at
+    once; a problem with a zero column stays singular."""
     rng = np.random.default_rng(N * 11 + n + P)
     A = np.stack([_rand_matrix(rng, N, n, P) for _ in range(3)])
     A[2, n // 2] = 0.0
     b = random_points(rng, 3, N, P)
-    try:
+    with _tune_restored(H, P, N):
         for grp in (8, 16, 32):
             res = {}
-            for mode in (0, 2):
+            for mode in (0, 2, 3):
                 H.tune_set(P, N, grp, mode)
                 Ad, bd = dev(A), dev(b)
                 dx, R, st = H.mgs_solve(Ad, bd)
                 res[mode] = (host(dx), host(R), host(st), host(Ad), host(bd))
             assert list(res[0][2]) == [H.OK, H.OK, H.ESINGULAR]
-            assert list(res[2][2]) == list(res[0][2])
-            for q in range(2):
-                for a0, a2 in zip(res[0], res[2]):
-                    if np.ndim(a0) > 1:
-                        assert _bitwise_equal(a0[q], a2[q]), (grp, q)
-    finally:
-        H.tune_set(P, N, 16, 0)
+            for mode in (2, 3):
+                assert list(res[mode][2]) == list(res[0][2])
+                for q in range(2):
+                    for a0, am in zip(res[0], res[mode]):
+                        if np.ndim(a0) > 1:
+                            assert _bitwise_equal(a0[q], am[q]), (grp, mode, q)
 
 
 # ---------------------------------------------------------------------------
@@ -833,6 +843,42 @@ def test_batch_split_alone_mix_and_oracle(H, P):
         assert (r1["status"], r1["steps"], r1["accepted"]) == (ro.status, ro.steps, ro.accepted), q
         scale = max(1.0, np.abs(lead_complex(xo)).max())
         assert np.abs(limb_diff(host(x1), xo)).max() <= 1e4 * GATE[P] * scale, q
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batch_panel_storage_bitwise(H, mixed):
+    """Slots whose table entry asks for the left-looking panel MGS (grouped
+    by rows per lane: 20, 40 and 70 rows at 8, 16 and 32 lanes) track to
+    bitwise the endpoints and step counts of the global-memory form at the
+    same lane-group width."""
+    P = 2
+    cases = []
+    for q, n in enumerate((20, 40, 70)):
+        rng = S.rng_for(3, 950 + q)
+        ps = S.random_system(rng, n, n, (2, 4), (1, 2), (1, 2), P, const_term=True)
+        cases.append((ps, S.random_unit_gamma(rng, P), S.start_solution(rng, S.degrees(ps), P)))
+    cases.append(_batch_cases(P)[0])
+    systems = [H.System(ps) for ps, _, _ in cases]
+    maxs = max(sd.info().nslots for sd in systems)
+    Ps = 1 if mixed else P
+    Ns = sorted({ps.N for ps, _, _ in cases})
+    out = {}
+    with _tune_restored(H, Ps, *Ns):
+        for grp in (8, 16, 32):
+            for mode in (0, 3):
+                for N in Ns:
+                    H.tune_set(Ps, N, grp, mode)
+                bt = H.Batch(P, capacity=5, max_n=70, max_nslots=maxs, mixed=mixed, max_steps=30)
+                for slot, ((ps, gam, x0), sd) in enumerate(zip(cases, systems)):
+                    bt.add(slot, sd, gam, dev(x0))
+                bt.run()
+                out[(grp, mode)] = [(host(x), r.tobytes())
+                                    for x, r in (bt.result(slot, ps.n)
+                                                 for slot, (ps, _, _) in enumerate(cases))]
+                bt.free()
+    for grp in (8, 16, 32):
+        for q, ((x0, r0), (x1, r1)) in enumerate(zip(out[(grp, 0)], out[(grp, 3)])):
+            assert r0 == r1 and _bitwise_equal(x0, x1), (grp, q)
 
 
 @pytest.mark.parametrize("P", [2, 4])
