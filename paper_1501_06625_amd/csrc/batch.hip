@@ -103,7 +103,7 @@ __global__ __launch_bounds__(256) void k_b_sum(BatchDev d, const int2 *work) {
     constexpr int W = 2 * limbs<R>::P;
     constexpr int WJ = VARIANT == BSUM_RESIDUAL ? 2 : W;  // element width of the matrix
     __shared__ double red[256 / 64];
-    const int2 w = work[blockIdx.x];
+    const int2 w = work[xcd_logical(blockIdx.x, gridDim.x)];
     const int slot = w.x;
     if (!d.st[slot].c_active) return;
     const SysView &s = d.sys[d.slot_sys[slot]];

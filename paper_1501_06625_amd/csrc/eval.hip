@@ -37,8 +37,11 @@ __global__ __launch_bounds__(256) void k_mon(MonArgs a) {
 template <class R>
 __global__ __launch_bounds__(256) void k_sum(SumArgs a) {
     __shared__ double red[256 / 64];
-    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int b = blockIdx.y; b < a.B; b += gridDim.y) {
+    // (part, point) from the XCD-aware logical id of the workgroup
+    const int L = xcd_logical(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
+    const int part = L % gridDim.x;
+    const long e = (long)part * blockDim.x + threadIdx.x;
+    for (int b = L / gridDim.x; b < a.B; b += gridDim.y) {
         if (a.st && !a.st[b].c_active) continue;
         SumOut o;
         o.jac = a.jac;
@@ -53,7 +56,7 @@ __global__ __launch_bounds__(256) void k_sum(SumArgs a) {
                                      t, a.hom.gamma, a.hom.gP, o);
         if (a.norm_part) {
             const double r = block_max(mx, red);
-            if (threadIdx.x == 0) a.norm_part[(size_t)b * gridDim.x + blockIdx.x] = r;
+            if (threadIdx.x == 0) a.norm_part[(size_t)b * gridDim.x + part] = r;
         }
     }
 }

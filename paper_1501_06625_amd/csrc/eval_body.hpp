@@ -28,6 +28,18 @@ namespace hcn {
 
 enum { MON_FREG = 0, MON_FSLOT = 1, MON_VALUES = 2 };
 
+// The dispatcher deals the workgroups of a launch to the 8 XCDs in turn
+// (linear id w to XCD w mod 8), and each XCD has an L2 of its own.  The
+// summation workgroups of one point share cache lines of its monomial
+// slots, so they are given logical ids that keep them on one XCD: XCD x
+// takes the contiguous range of logical ids starting at x (G / 8) +
+// min(x, G mod 8), in dispatch order.  A bijection of 0..G-1.
+HCN_DEV int xcd_logical(int w, int G) {
+    constexpr int X = 8;
+    const int x = w % X, q = G / X, r = G % X;
+    return x * q + (x < r ? x : r) + w / X;
+}
+
 // The point a monomial kernel reads: variable v at x + v * stride, xP limbs
 // (at least those of the compute precision).  pows (LDS, or NULL when the
 // largest exponent is at most 2): pows + ((j - 2) n + v) W holds y_v^j for
@@ -185,13 +197,40 @@ HCN_DEV void mon_one(const SysView &s, int m, const PointView &pv, double *out) 
     cstore(out + (size_t)(slot + stride) * W, escale(Bk, s.ex[m]));
 }
 
+// The sum of the slots list[0], list[step], ..., list[(len-1) step], added
+// in list order.  The slot loads of SUM_BATCH entries (8; 4 in QD, whose
+// slots take twice the registers) are issued before their additions, so
+// that each lane keeps that many gathers in flight instead of one; the
+// order of the additions, and so every bit, is that of the plain loop.
+template <class R>
+HCN_DEV cx<R> sum_strided(const double *sc, const int32_t *list, int step, int len) {
+    constexpr int W = 2 * limbs<R>::P;
+    constexpr int SUM_BATCH = limbs<R>::P == 4 ? 4 : 8;
+    cx<R> acc = czero<R>();
+    int c = 0;
+    for (; c + SUM_BATCH <= len; c += SUM_BATCH) {
+        cx<R> v[SUM_BATCH];
+#pragma unroll
+        for (int u = 0; u < SUM_BATCH; ++u) v[u] = cload<R>(sc + (size_t)list[(c + u) * step] * W);
+#pragma unroll
+        for (int u = 0; u < SUM_BATCH; ++u) acc = c + u == 0 ? v[u] : cadd(acc, v[u]);
+    }
+    if (c < len) {
+        const int rem = len - c;
+        cx<R> v[SUM_BATCH];
+#pragma unroll
+        for (int u = 0; u < SUM_BATCH; ++u)
+            if (u < rem) v[u] = cload<R>(sc + (size_t)list[(c + u) * step] * W);
+#pragma unroll
+        for (int u = 0; u < SUM_BATCH; ++u)
+            if (u < rem) acc = c + u == 0 ? v[u] : cadd(acc, v[u]);
+    }
+    return acc;
+}
+
 template <class R>
 HCN_DEV cx<R> sum_list(const double *sc, const int32_t *list, int a, int b) {
-    constexpr int W = 2 * limbs<R>::P;
-    if (a >= b) return czero<R>();
-    cx<R> acc = cload<R>(sc + (size_t)list[a] * W);
-    for (int q = a + 1; q < b; ++q) acc = cadd(acc, cload<R>(sc + (size_t)list[q] * W));
-    return acc;
+    return a >= b ? czero<R>() : sum_strided<R>(sc, list + a, 1, b - a);
 }
 
 template <class R>
@@ -229,12 +268,7 @@ HCN_DEV double sum_one(const SysView &s, long e, const double *sc, const double 
         // the interleaved copy of the list: lanes of a wavefront read their
         // c-th indices from consecutive words
         const int32_t *li = s.J_ilv + s.J_wbase[e >> 6] + (e & 63);
-        const int len = s.J_ptr[e + 1] - s.J_ptr[e];
-        acc = czero<R>();
-        for (int c = 0; c < len; ++c) {
-            const cx<R> v = cload<R>(sc + (size_t)li[64 * c] * W);
-            acc = c == 0 ? v : cadd(acc, v);
-        }
+        acc = sum_strided<R>(sc, li, 64, s.J_ptr[e + 1] - s.J_ptr[e]);
     } else {
         acc = isJ ? sum_list<R>(sc, s.J_list, s.J_ptr[e], s.J_ptr[e + 1])
                   : sum_list<R>(sc, s.f_list, s.f_ptr[i], s.f_ptr[i + 1]);
