@@ -38,15 +38,20 @@ if ROOT not in sys.path:
 
 FP64_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 # HBM traffic per launch of the dense-DD kernels at 10240 points, from
-# rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this leg (KiB per dispatch),
-# calibrated on the 10 MiB copy of the start points in the same runs
-# (FETCH_SIZE reads 5132.5 KiB, WRITE_SIZE 10240 KiB for 10,485,760 bytes);
-# valid for the MGS configuration they were taken with and for the kernels as
-# they are now (summary and commands: profiles/newton_step_dense32_dd_b10240.md)
-HBM_COUNTERS_KIB = {"mgs": {(8, 0): (1404683.4, 5403123.4), (16, 0): (835265.3, 4592624.3)},
-                    "eval_monomials": (36559.8, 5570564.0), "eval_sums": (6102775.6, 339643.5)}
+# rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this leg (KiB per dispatch; the
+# MGS per lane-group width and storage of [A | b], from the autotuner's
+# launches), calibrated on the 10 MiB copy of the start points in the same
+# runs (FETCH_SIZE reads 5131.5 KiB, WRITE_SIZE 10240 KiB for 10,485,760
+# bytes); valid for the kernels as they are now (summary and commands:
+# profiles/newton_step_dense32_dd_b10240.md)
+HBM_COUNTERS_KIB = {
+    "mgs": {(8, 0): (945157.6, 5453032.7), (8, 1): (274861.6, 205512.0), (8, 2): (275001.8, 206140.7),
+            (8, 3): (437254.4, 542531.0), (16, 0): (885618.4, 4779626.7), (16, 1): (274882.0, 205953.5),
+            (16, 2): (275021.1, 205777.8), (16, 3): (452625.2, 540710.9), (32, 0): (784480.7, 3993257.2),
+            (32, 1): (274894.0, 208023.4), (32, 3): (480647.3, 537131.4)},
+    "eval_monomials": (38058.0, 5570560.0), "eval_sums": (4441688.5, 339787.0)}
 MGS_PIN = None  # (lane group, storage) from --mgs-group / --mgs-storage, else autotuned
-FETCH_CAL, WRITE_CAL = 10485760 / (5132.5 * 1024), 1.0
+FETCH_CAL, WRITE_CAL = 10485760 / (5131.5 * 1024), 1.0
 _T0 = time.time()
 
 
