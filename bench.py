@@ -271,7 +271,8 @@ def serve_leg(hcn, S, dev, pool: int = 32, burst: int = 384, poisson: int = 384,
             "poisson_0.8": lat, "one_at_a_time": base}
 
 
-def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10) -> dict:
+def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10,
+              split_n: int = 0) -> dict:
     """64 random systems (n in [16, 96], 16..64 monomials per equation, 4..12
     variables per monomial, exponents 1..3), 64 total-degree start solutions
     each: 4096 paths in one slot-table batch, tracked in complex DD for a
@@ -307,7 +308,8 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
     progress("batch: systems and start points ready")
     for mode in ("plain", "mixed"):
         progress(f"batch: {mode}")
-        bt = hcn.Batch(2, nsys * per, max_n, max_slots, max_systems=nsys, mixed=(mode == "mixed"))
+        bt = hcn.Batch(2, nsys * per, max_n, max_slots, max_systems=nsys, mixed=(mode == "mixed"),
+                       split_n=split_n)
         for s in range(nsys):
             for q in range(per):
                 bt.add(s * per + q, loaded[s], gammas[s], starts[s][q])
