@@ -224,6 +224,54 @@ def test_monomials_uniform_form_bitwise(H, P):
         H.set_mon_uniform(True)
 
 
+def test_empty_batches_are_noops(H):
+    """Zero points: every entry point returns at once with empty outputs."""
+    import torch
+    for P in (2, 4):
+        ps = S.small_track_system(3, P)
+        sysd = H.System(ps)
+        x = torch.zeros((0, ps.n, 2, P), dtype=torch.float64, device="cuda")
+        f, J = H.eval_jac(sysd, x)
+        assert f.shape[0] == 0 and J.shape[0] == 0
+        norms, st = H.newton_step(sysd, x)
+        assert norms.shape[0] == 0 and st.shape[0] == 0
+        for mixed in (False, True):
+            st, it, nm = H.newton(sysd, x, mixed=mixed)
+            assert st.shape[0] == 0
+        xo, res = H.track_paths(sysd, S.random_unit_gamma(S.rng_for(0, 1), P), x)
+        assert xo.shape[0] == 0 and len(res) == 0
+        sysd.free()
+
+
+def test_points_beyond_one_grid_row(H):
+    """More points than one grid dimension holds (65535): the launches loop
+    over the rest, and every point gets bitwise what it gets in a small
+    batch (evaluation, one Newton step, the Fig. 2 loop)."""
+    P = 2
+    ps = S.small_track_system(5, P)
+    rng = np.random.default_rng(65536)
+    B = 70000
+    xs = random_points(rng, B, ps.n, P)
+    sysd = H.System(ps)
+    f, J = H.eval_jac(sysd, dev(xs))
+    xd = dev(xs)
+    nm1, st1 = H.newton_step(sysd, xd)
+    xl = dev(xs)
+    st, it, nm = H.newton(sysd, xl)
+    f, J, xd, nm1, xl, st = host(f), host(J), host(xd), host(nm1), host(xl), host(st)
+    for lo in (0, 65530, B - 7):
+        sl = slice(lo, lo + 7)
+        fs, Js = H.eval_jac(sysd, dev(xs[sl]))
+        assert _bitwise_equal(host(fs), f[sl]) and _bitwise_equal(host(Js), J[sl]), lo
+        xq = dev(xs[sl])
+        nq, _ = H.newton_step(sysd, xq)
+        assert _bitwise_equal(host(xq), xd[sl]) and _bitwise_equal(host(nq), nm1[sl]), lo
+        xq = dev(xs[sl])
+        sq, _, _ = H.newton(sysd, xq)
+        assert _bitwise_equal(host(xq), xl[sl]) and np.array_equal(host(sq), st[sl]), lo
+    sysd.free()
+
+
 def test_eval_batch_independent_and_deterministic(H):
     ps = S.dense32_system(0, 2)
     xs = S.dense32_points(1, 6, 2)
@@ -371,9 +419,11 @@ def test_newton_fig2_decisions(H):
 # ---------------------------------------------------------------------------
 
 @pytest.mark.parametrize("P", [2, 4])
-def test_track_closed_form_powers(H, P):
-    rng = S.rng_for(6, 50 + P)
-    n, d = 4, 3
+@pytest.mark.parametrize("n,d", [(4, 3), (1, 5)])
+def test_track_closed_form_powers(H, P, n, d):
+    """x_i^d = c_i (one variable, or several uncoupled ones): the endpoints
+    are the closed-form ones and the step decisions the oracle's."""
+    rng = S.rng_for(6, 50 + P + (0 if n == 4 else 100))
     cs = S.unit_complex(rng.uniform(0, 6.28, n), P)
     ps = S.diagonal_power_system(cs, d, P)
     gam = S.random_unit_gamma(rng, P)
