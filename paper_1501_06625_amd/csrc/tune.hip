@@ -34,12 +34,16 @@ int nbucket(int N) {
     return b;
 }
 
-// untuned: 16 lanes per column; beyond 32 rows (DD and FP64, while a
-// column fits 16 rows per lane) the left-looking panel form, which reads
-// [A | b] once instead of the trailing matrix at every column step
+// untuned: 16 lanes per column; from 33 to 256 rows in DD and FP64 the
+// left-looking panel form, which reads [A | b] once instead of the trailing
+// matrix at every column step, with 32 lanes per column beyond 128 rows
+// (at most 8 rows per lane: 16 take every register of a lane)
 Choice default_choice(int P, int N) {
     Choice c;
-    if (P != 4 && N > 32 && N <= 256 && mgs_panel_rpl(N, P, 16) > 0) c.lds = 3;
+    if (P != 4 && N > 32 && N <= 256) {
+        c.group = N > 128 ? 32 : 16;
+        c.lds = 3;
+    }
     return c;
 }
 
