@@ -104,7 +104,8 @@ def cpu_baseline(target_s: float = 15.0) -> dict:
                       f"({per_thread} per thread on {cores} threads), {wall:.1f} s wall"}
 
 
-def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single")) -> dict:
+def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single"),
+            sparse_variants=None) -> dict:
     import numpy as np
     import torch
     from paper_1501_06625_amd import flops, hcn, systems as S
@@ -168,7 +169,7 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single"))
         out["single"] = leg(2, 1, 200, 5, profile=False)
     if "sparse512" in legs:
         progress("sparse n=512 leg")
-        out["sparse512"] = sparse512_leg(hcn, flops, S, dev)
+        out["sparse512"] = sparse512_leg(hcn, flops, S, dev, variants=sparse_variants)
     if "batch64" in legs:
         progress("64-system batch leg")
         out["batch64"] = batch_leg(hcn, flops, S, dev)
@@ -349,10 +350,11 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
     return res
 
 
-def sparse512_leg(hcn, flops, S, dev, reps: int = 10) -> dict:
+def sparse512_leg(hcn, flops, S, dev, reps: int = 10, variants=None) -> dict:
     """Sparse n = 512 system (4 monomials of 2 variables + a constant per
-    equation): one Newton step of one point, timed per MGS variant.  The
-    solve dominates (17.2 GFLOP of MGS against 1 MFLOP of evaluation)."""
+    equation): one Newton step of one point, timed per MGS variant (all, or
+    the names in variants).  The solve dominates (17.2 GFLOP of MGS against
+    1 MFLOP of evaluation)."""
     import torch
     ps = S.sparse512_system(0, 2)
     pts = S.random_unit_point(S.rng_for(2, 99), ps.n, 2)[None]
@@ -365,6 +367,8 @@ def sparse512_leg(hcn, flops, S, dev, reps: int = 10) -> dict:
     runs = [(1, 16, "workgroup"), (2, 16, "right_looking"), (3, 16, "column_resident"),
             (4, 16, "tiled_T16"), (4, 8, "tiled_T8"), (4, 4, "tiled_T4")]
     for v, T, name in runs:
+        if variants and name not in variants:
+            continue
         hcn.set_mgs_variant(v)
         hcn.set_mgs_panel(T)
         x.copy_(x0)
@@ -406,7 +410,10 @@ def main() -> int:
     ap.add_argument("--mgs-storage", type=int, default=0,
                     help="with --mgs-group: [A | b] in global memory (0), LDS (1) or registers (2)")
     ap.add_argument("--legs", default="dd,qd,single,sparse512,batch64,serve",
-                    help="comma list of dd (the reported line), qd, single; profiling runs use one")
+                    help="comma list of dd (the reported line), qd, single, sparse512, batch64, serve")
+    ap.add_argument("--sparse512-variants", default=None,
+                    help="comma list of MGS variants for the sparse512 leg (workgroup, right_looking, "
+                         "column_resident, tiled_T16, tiled_T8, tiled_T4); default all")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -425,7 +432,8 @@ def main() -> int:
     legs = tuple(args.legs.split(","))
     if "dd" not in legs:
         legs = ("dd",) + legs
-    r = run_gpu(args.steps, args.warmup, args.qd_steps, legs)
+    sv = tuple(args.sparse512_variants.split(",")) if args.sparse512_variants else None
+    r = run_gpu(args.steps, args.warmup, args.qd_steps, legs, sv)
     dd = r["dd"]
     ms = dd["ms_per_step"]
     value = dd["B"] / (ms / 1e3)
