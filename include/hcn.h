@@ -183,8 +183,8 @@ int hcn_set_chunk_bytes(size_t bytes);
  * Problems of batches of at most 64 use 2 when it fits.  Per precision P
  * (1 = the FP64 solve of the mixed-precision step, 2, 4)
  * and row count N (bucketed to the next power of two >= 8).  Defaults: for
- * DD and FP64 with 32 < N <= 256 storage 3 (16 lanes up to N = 128, 32
- * beyond), else 16 lanes and global memory.
+ * DD and FP64 with 32 < N <= 256 storage 3 (16 lanes up to N = 128 in DD and
+ * N = 64 in FP64, 32 beyond), else 16 lanes and global memory.
  * Every choice gives bitwise the same results, and it depends
  * only on (P, N), so a problem's result does not depend on the batch it is
  * solved in.  save/load: text, one "P N group lds" line per entry.

@@ -36,12 +36,13 @@ int nbucket(int N) {
 
 // untuned: 16 lanes per column; from 33 to 256 rows in DD and FP64 the
 // left-looking panel form, which reads [A | b] once instead of the trailing
-// matrix at every column step, with 32 lanes per column beyond 128 rows
-// (at most 8 rows per lane: 16 take every register of a lane)
+// matrix at every column step, with 32 lanes per column beyond 128 rows in
+// DD (at most 8 rows per lane: 16 take every register of a lane) and beyond
+// 64 rows in FP64 (the solve of the mixed-precision corrector)
 Choice default_choice(int P, int N) {
     Choice c;
     if (P != 4 && N > 32 && N <= 256) {
-        c.group = N > 128 ? 32 : 16;
+        c.group = N > (P == 1 ? 64 : 128) ? 32 : 16;
         c.lds = 3;
     }
     return c;
