@@ -167,6 +167,9 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs=("dd", "qd", "single"),
         # single-path latency: one Newton step of one point, stream-ordered
         progress("single-path leg")
         out["single"] = leg(2, 1, 200, 5, profile=False)
+    if "track8" in legs:
+        progress("single-path tracking leg (n = 8)")
+        out["track8"] = track8_leg(hcn, S, dev)
     if "sparse512" in legs:
         progress("sparse n=512 leg")
         out["sparse512"] = sparse512_leg(hcn, flops, S, dev, variants=sparse_variants)
@@ -350,6 +353,49 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
     return res
 
 
+def track8_leg(hcn, S, dev, seeds: int = 8) -> dict:
+    """One path at a time: random n = 8 systems (8 monomials per equation of
+    3 distinct variables, exponents 1..2), each path tracked from x = 1 at
+    t = 0 to t = 1 (secant predictor, at most 3 Newton iterations a step,
+    end-point refinement) by the single-system tracker, by a one-slot batch
+    replaying its captured step, and by a one-slot batch with one persistent
+    workgroup; wall time per path from the host (the run ends with the
+    result on the host)."""
+    import numpy as np
+    import torch
+    modes = ("tracker", "batch_graph", "batch_persistent")
+    per = {m: [] for m in modes}
+    steps, ok = [], 0
+    for seed in range(seeds):
+        ps = S.small_track_system(seed, 2)
+        sd = hcn.System(ps)
+        gam = S.random_unit_gamma(S.rng_for(0, 100 + seed), 2)
+        x0 = torch.from_numpy(S.ones_point(ps.n, 2)).to(dev)
+        for m in modes:
+            for rep in range(2):  # the first run of each mode warms up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if m == "tracker":
+                    _, r = hcn.track_paths(sd, gam, x0[None])
+                    r = r[0]
+                else:
+                    bt = hcn.Batch(2, 1, ps.n, sd.info().nslots, persistent=(m == "batch_persistent"))
+                    bt.add(0, sd, gam, x0)
+                    bt.run(chunk=32)
+                    _, r = bt.result(0, ps.n)
+                    bt.free()
+                dt = time.perf_counter() - t0
+            per[m].append((dt, int(r["steps"])))
+        steps.append(int(r["steps"]))
+        ok += int(r["status"] == 0)
+        sd.free()
+    res = {"paths": seeds, "ok": ok, "steps": steps}
+    for m in modes:
+        res[m] = {"ms_per_path_median": float(np.median([d for d, _ in per[m]]) * 1e3),
+                  "us_per_step": float(sum(d for d, _ in per[m]) / max(sum(k for _, k in per[m]), 1) * 1e6)}
+    return res
+
+
 def sparse512_leg(hcn, flops, S, dev, reps: int = 10, variants=None) -> dict:
     """Sparse n = 512 system (4 monomials of 2 variables + a constant per
     equation): one Newton step of one point, timed per MGS variant (all, or
@@ -409,8 +455,8 @@ def main() -> int:
                     help="pin the MGS lane-group width (8/16/32) instead of autotuning")
     ap.add_argument("--mgs-storage", type=int, default=0,
                     help="with --mgs-group: [A | b] in global memory (0), LDS (1) or registers (2)")
-    ap.add_argument("--legs", default="dd,qd,single,sparse512,batch64,serve",
-                    help="comma list of dd (the reported line), qd, single, sparse512, batch64, serve")
+    ap.add_argument("--legs", default="dd,qd,single,track8,sparse512,batch64,serve",
+                    help="comma list of dd (the reported line), qd, single, track8, sparse512, batch64, serve")
     ap.add_argument("--sparse512-variants", default=None,
                     help="comma list of MGS variants for the sparse512 leg (workgroup, right_looking, "
                          "column_resident, tiled_T16, tiled_T8, tiled_T4); default all")
@@ -500,6 +546,7 @@ def main() -> int:
             "pct_fp64_peak": 100.0 * qd["flops"]["total"] * qd["B"] /
             (qd["ms_per_step"] / 1e3) / 1e12 / FP64_PEAK_TFLOPS},
         "single_path_us_per_newton_step": None if single is None else single["ms_per_step"] * 1e3,
+        "track8": r.get("track8"),
         "sparse512": r.get("sparse512"),
         "batch64": r.get("batch64"),
         "serve": r.get("serve"),

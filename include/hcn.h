@@ -341,6 +341,18 @@ int hcn_batch_release(hcn_batch b, int slot);
  * Takes effect at the next step.  EINVAL for a NULL batch or min_n < 0. */
 int hcn_batch_set_split(hcn_batch b, int min_n);
 
+/* How hcn_batch_step runs plain steps (default 0): 0 a captured graph of
+ * the step's launches (monomials, sums and solve over all slots), replayed
+ * once per step; 1 one persistent workgroup per slot that runs the requested
+ * steps of its own path, stage after stage, without returning to the host,
+ * and stops when its path is done: no launch or graph overhead per stage,
+ * for small systems and few paths (Section 2: a single path is latency
+ * bound).  Both give bitwise the same results.  The persistent form covers
+ * the plain corrector with the one-workgroup solve; a batch in mixed
+ * precision or with slots on the tiled solve (hcn_batch_set_split) keeps the
+ * graph.  EINVAL for a NULL batch. */
+int hcn_batch_set_persistent(hcn_batch b, int on);
+
 /* Enqueue `steps` predictor-corrector steps of every unfinished path. */
 int hcn_batch_step(hcn_batch b, int steps, void *stream);
 

@@ -201,6 +201,68 @@ __global__ __launch_bounds__(MGS_THREADS) void k_b_mgs_panel(BatchDev d, const i
     mgs_panel<R, GRP, RPL>(slot_problem<R>(d, slots[blockIdx.x]));
 }
 
+// Persistent form of a plain step for one slot per workgroup: begin, then
+// max_iter times {monomials, sums, one-workgroup MGS with the Fig. 2 tests},
+// then end; the same device functions on the same data in the same order as
+// the launches of a captured step, so a path gets bitwise the same results.
+// The workgroup runs up to `steps` steps of its path without returning to
+// the host, and stops once the path is done (every later step would leave a
+// finished path unchanged).  The monomials take the general form (forward
+// products parked in their output slots, any size up to 64 variables,
+// exponents by branching), which gives the same bits as the register and
+// uniform forms of the captured step and keeps this kernel to one instance
+// per precision and lane-group width.  The dynamic LDS holds [A | b] during
+// a solve staged in LDS.
+template <class R>
+HCN_DEV void b_sum_full(const BatchDev &d, int slot, const SysView &s, int nparts, double *red) {
+    constexpr int W = 2 * limbs<R>::P;
+    double *J = d.J + (size_t)slot * d.Js;
+    SumOut o;
+    o.jac = 1;
+    o.J = J;
+    o.J_cstride = (long)s.N * W;
+    o.f = J + (size_t)s.n * s.N * W;
+    o.f_neg = 1;
+    o.f_lead_only = 0;
+    for (int part = 0; part < nparts; ++part) {
+        const long e = (long)part * 256 + threadIdx.x;
+        const double mx = sum_one<R>(s, e, d.sc + (size_t)slot * d.scs, d.x + (size_t)slot * d.xs, d.P,
+                                     1, d.relax_k, d.t[slot], d.gamma + (size_t)slot * 2 * d.P, d.P, o);
+        const double r = block_max(mx, red);
+        if (threadIdx.x == 0) d.np[(size_t)slot * d.nps + part] = r;
+    }
+}
+
+template <class R, int GRP>
+__global__ __launch_bounds__(MGS_THREADS) void k_b_persist(BatchDev d, const int *slots, int steps) {
+    __shared__ double red[256 / 64];
+    const int slot = slots[blockIdx.x];
+    const TrackPath path = slot_path(d, slot);
+    const SysView &s = d.sys[d.slot_sys[slot]];
+    const double *xb = d.x + (size_t)slot * d.xs;
+    double *sc = d.sc + (size_t)slot * d.scs;
+    const int nparts = (int)(((long)s.n * s.N + s.N + 255) / 256);
+    for (int q = 0; q < steps; ++q) {
+        __syncthreads();
+        if (d.st[slot].phase == PHASE_DONE) return;
+        track_begin_one<R>(d.prm, path);
+        for (int it = 0; it < d.prm.max_iter; ++it) {
+            // the state written by one lane is read by all after a barrier
+            __syncthreads();
+            if (d.st[slot].c_active) {
+                const PointView pv{xb, 2 * d.P, d.P, nullptr};
+                for (int m = threadIdx.x; m < s.nmon; m += MGS_THREADS) mon_one<R, 64, MON_FSLOT, false>(s, m, pv, sc);
+                __syncthreads();
+                b_sum_full<R>(d, slot, s, nparts, red);
+                __syncthreads();
+            }
+            mgs_wg<R, GRP>(slot_problem<R>(d, slot));
+        }
+        __syncthreads();
+        track_end_one<R>(d.prm, path);
+    }
+}
+
 // tiled MGS of the large slots: the Fig. 2 tests before the solve (already
 // taken by the residual pass in mixed mode) and a cleared singular flag
 __global__ void k_bt_pre(BatchDev d, const int *slots, int count) {
@@ -317,6 +379,8 @@ struct hcn_batch_s {
     int n_mon = 0, n_sum = 0, n_sumf = 0, n_slots = 0;
     // large slots (n >= split_n; 0: none) solve with the tiled MGS
     int split_n = 0;
+    // plain steps as one persistent workgroup per slot (no tiled slots)
+    bool persistent = false;
     int *d_big = nullptr;
     int n_big = 0, big_maxn = 0, big_maxN = 0;
     // one-workgroup MGS launches: lane-group width index g (8, 16, 32) times
@@ -428,6 +492,31 @@ void launch_b_mgs(hcn_batch_s *b, hipStream_t s) {
     launch_b_mgs_grp<R, 8>(b, 0, s);
     launch_b_mgs_grp<R, 16>(b, 1, s);
     launch_b_mgs_grp<R, 32>(b, 2, s);
+}
+
+// `steps` plain steps of every slot by the persistent kernels, one launch
+// per lane-group width (the slots of one width are contiguous in the list)
+template <class R>
+int enqueue_persist(hcn_batch_s *b, int steps, hipStream_t s) {
+    const int lim = (int)mgs_lds_limit();
+    for (int g = 0; g < 3; ++g) {
+        int cnt = 0;
+        for (int f = 0; f < NFORM; ++f) cnt += b->grp_cnt[g * NFORM + f];
+        if (cnt == 0) continue;
+        const int *list = b->d_slots + b->grp_off[g * NFORM];
+        const size_t lds = b->grp_lds[g * NFORM];
+        const dim3 grid(cnt), block(MGS_THREADS);
+        const void *fn = g == 0 ? (const void *)k_b_persist<R, 8>
+                       : g == 1 ? (const void *)k_b_persist<R, 16> : (const void *)k_b_persist<R, 32>;
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+        if (g == 0)
+            hipLaunchKernelGGL((k_b_persist<R, 8>), grid, block, lds, s, b->d, list, steps);
+        else if (g == 1)
+            hipLaunchKernelGGL((k_b_persist<R, 16>), grid, block, lds, s, b->d, list, steps);
+        else
+            hipLaunchKernelGGL((k_b_persist<R, 32>), grid, block, lds, s, b->d, list, steps);
+    }
+    return (int)hipGetLastError();
 }
 
 template <class R>
@@ -730,6 +819,12 @@ int hcn_batch_set_split(hcn_batch b, int min_n) {
     return HCN_OK;
 }
 
+int hcn_batch_set_persistent(hcn_batch b, int on) {
+    if (!b) return bfail(HCN_EINVAL, "hcn_batch_set_persistent: NULL batch");
+    b->persistent = on != 0;
+    return HCN_OK;
+}
+
 int hcn_batch_release(hcn_batch b, int slot) {
     if (!b || slot < 0 || slot >= b->cap) return bfail(HCN_EINVAL, "hcn_batch_release: bad slot");
     b->slot_sys[slot] = -1;
@@ -747,6 +842,11 @@ int hcn_batch_step(hcn_batch b, int steps, void *stream) {
         if (rc) return rc;
     }
     if (b->n_slots == 0 || steps == 0) return HCN_OK;
+    if (b->persistent && !b->d.mixed && b->n_big == 0) {
+        ProfScope prof("batch_step", s);
+        const int e = b->P == 2 ? enqueue_persist<dd>(b, steps, s) : enqueue_persist<qd>(b, steps, s);
+        return e ? bfail(HCN_EDEVICE, "hcn_batch_step: persistent launch failed") : HCN_OK;
+    }
     // the graph is captured and replayed on the caller's stream; the legacy
     // null stream cannot be captured, so its callers go through the batch's
     // own stream, joined with events on both sides

@@ -66,7 +66,7 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_set_chunk_bytes", "hcn_set_mon_uniform", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
            "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load", "hcn_autotune",
            "hcn_batch_create", "hcn_batch_destroy", "hcn_batch_device_bytes",
-           "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_set_split", "hcn_batch_step",
+           "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_set_split", "hcn_batch_set_persistent", "hcn_batch_step",
            "hcn_batch_poll", "hcn_batch_result", "hcn_batch_run", "hcn_batch_counts",
            "hcn_server_create", "hcn_server_destroy", "hcn_server_last_error", "hcn_server_now",
            "hcn_server_capacity", "hcn_server_submit", "hcn_server_pump", "hcn_server_fetch",
@@ -123,6 +123,7 @@ def _load():
     lib.hcn_batch_add.argtypes = [vp, ci, vp, vp, vp, vp]
     lib.hcn_batch_release.argtypes = [vp, ci]
     lib.hcn_batch_set_split.argtypes = [vp, ci]
+    lib.hcn_batch_set_persistent.argtypes = [vp, ci]
     lib.hcn_batch_step.argtypes = [vp, ci, vp]
     lib.hcn_batch_poll.argtypes = [vp, vp, vp]
     lib.hcn_batch_result.argtypes = [vp, ci, vp, vp, vp]
@@ -465,7 +466,7 @@ class Batch:
 
     def __init__(self, P: int, capacity: int, max_n: int, max_nslots: int,
                  max_systems: int = 256, relax_k: int = 1, mixed: bool = False,
-                 split_n: int = 0, **track_kw):
+                 split_n: int = 0, persistent: bool = False, **track_kw):
         self.P = P
         self.capacity = capacity
         self.prm = track_params(P, **track_kw)
@@ -476,6 +477,8 @@ class Batch:
         self.handle = h
         if split_n:
             _bcheck(_lib.hcn_batch_set_split(h, int(split_n)))
+        if persistent:
+            _bcheck(_lib.hcn_batch_set_persistent(h, 1))
         self._keep = {}
         self.device = torch.device("cuda", torch.cuda.current_device())
 

@@ -49,6 +49,7 @@ def test_host_side_argument_errors():
     assert lib.hcn_set_mgs_panel(0) == hcn.EINVAL
     assert lib.hcn_set_mgs_panel(17) == hcn.EINVAL
     assert lib.hcn_tune_set(2, 32, 16, 5) == hcn.EINVAL
+    assert lib.hcn_batch_set_persistent(None, 1) == hcn.EINVAL
     assert lib.hcn_tune_set(2, 32, 12, 0) == hcn.EINVAL
     # a repeated variable inside a monomial is rejected
     eq_ptr = np.array([0, 1], dtype=np.int32)

@@ -826,6 +826,39 @@ def test_batch_matches_single_system_tracking(H, P):
     bt2.free()
 
 
+@pytest.mark.parametrize("P", [2, 4])
+def test_batch_persistent_bitwise(H, P):
+    """One persistent workgroup per slot gives bitwise the endpoints, step
+    counts and work counters of the captured graph, for paths of several
+    systems (some finishing long before others), stepped a few steps at a
+    time or run to the end, and for a single path alone."""
+    cases = _batch_cases(P)
+    systems = {id(c[0]): H.System(c[0]) for c in cases}
+    maxs = max(sd.info().nslots for sd in systems.values())
+    out = {}
+    for persistent in (False, True):
+        bt = H.Batch(P, capacity=len(cases) + 1, max_n=8, max_nslots=maxs, persistent=persistent)
+        for slot, (ps, gam, x0) in enumerate(cases):
+            bt.add(slot + 1, systems[id(ps)], gam, dev(x0))
+        bt.step(3)
+        mid = bt.poll()
+        bt.run(chunk=5)
+        res = [bt.result(slot + 1, ps.n) for slot, (ps, _, _) in enumerate(cases)]
+        out[persistent] = (mid[0], [(host(x), r.tobytes()) for x, r in res], bt.counts().tobytes())
+        bt.free()
+        b1 = H.Batch(P, capacity=1, max_n=8, max_nslots=maxs, persistent=persistent)
+        ps, gam, x0 = cases[2]
+        b1.add(0, systems[id(ps)], gam, dev(x0))
+        b1.run(chunk=64)
+        x, r = b1.result(0, ps.n)
+        out[persistent] += ((host(x), r.tobytes()),)
+        b1.free()
+    g, p = out[False], out[True]
+    assert g[0] == p[0] and g[2] == p[2]
+    for (xg, rg), (xp, rp) in zip(g[1] + [g[3]], p[1] + [p[3]]):
+        assert rg == rp and _bitwise_equal(xg, xp)
+
+
 def test_batch_step_by_step_polling(H):
     """Stepping a few steps at a time and polling reports progress."""
     P = 2
