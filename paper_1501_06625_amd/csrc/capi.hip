@@ -261,27 +261,38 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
                 }
             }
     }
-    // the same lists interleaved per wavefront of 64 consecutive entries
-    // (entry c of entry e at J_wbase[e / 64] + 64 c + e % 64), so that the
-    // lanes of a wavefront read their c-th slot indices from one cache line;
-    // dropped when the padding to each wavefront's longest list would cost
-    // more than four times the lists
+    // The summation takes the Jacobian entries equation-major: lane index
+    // q = i n + k forms entry (k, i), whose list is that of e = k N + i.  The
+    // partials of neighbouring monomials share cache lines (slots are
+    // position-major within a size group) and belong, mostly, to one
+    // equation, so their lines are read by lanes of one wavefront at nearly
+    // the same list position.  The lists are interleaved per wavefront of 64
+    // consecutive lanes (entry c of lane q at J_wbase[q / 64] + 64 c +
+    // q % 64), so that the lanes read their c-th slot indices from one cache
+    // line; the copy is dropped when the padding to each wavefront's longest
+    // list would cost more than four times the lists.
+    auto lane_entry = [&](long q) -> long { return (q % n) * N + q / n; };
     const long nwv = (nJ + 63) / 64;
     std::vector<int32_t> J_wbase(nwv + 1, 0), J_ilv;
     {
         long total = 0;
         for (long w = 0; w < nwv; ++w) {
             int mx = 0;
-            for (long e = w * 64; e < std::min(nJ, (w + 1) * 64); ++e) mx = std::max(mx, J_ptr[e + 1] - J_ptr[e]);
+            for (long q = w * 64; q < std::min(nJ, (w + 1) * 64); ++q) {
+                const long e = lane_entry(q);
+                mx = std::max(mx, J_ptr[e + 1] - J_ptr[e]);
+            }
             total += 64L * mx;
             if (total > (1L << 30)) break;
             J_wbase[w + 1] = (int32_t)total;
         }
         if (total <= 4L * std::max(npairs, 1) + 4096) {
             J_ilv.assign(std::max<long>(total, 1), 0);
-            for (long e = 0; e < nJ; ++e)
+            for (long q = 0; q < nJ; ++q) {
+                const long e = lane_entry(q);
                 for (int c = 0; c < J_ptr[e + 1] - J_ptr[e]; ++c)
-                    J_ilv[J_wbase[e / 64] + 64L * c + e % 64] = J_list[J_ptr[e] + c];
+                    J_ilv[J_wbase[q / 64] + 64L * c + q % 64] = J_list[J_ptr[e] + c];
+            }
         }
     }
     std::vector<int32_t> deg(N, 0);

@@ -261,16 +261,19 @@ HCN_DEV double sum_one(const SysView &s, long e, const double *sc, const double 
     const long nJ = o.jac ? (long)s.n * s.N : 0;
     if (e >= nJ + s.N) return 0.0;
     const bool isJ = e < nJ;
-    const int k = isJ ? (int)(e / s.N) : -1;
-    const int i = isJ ? (int)(e % s.N) : (int)(e - nJ);
+    // Jacobian lanes equation-major: lane e forms entry (k, i) = (e mod n,
+    // e / n), whose list is that of the column-major index ej = k N + i
+    const int k = isJ ? (int)(e % s.n) : -1;
+    const int i = isJ ? (int)(e / s.n) : (int)(e - nJ);
+    const long ej = (long)k * s.N + i;
     cx<R> acc;
     if (isJ && s.J_ilv) {
         // the interleaved copy of the list: lanes of a wavefront read their
         // c-th indices from consecutive words
         const int32_t *li = s.J_ilv + s.J_wbase[e >> 6] + (e & 63);
-        acc = sum_strided<R>(sc, li, 64, s.J_ptr[e + 1] - s.J_ptr[e]);
+        acc = sum_strided<R>(sc, li, 64, s.J_ptr[ej + 1] - s.J_ptr[ej]);
     } else {
-        acc = isJ ? sum_list<R>(sc, s.J_list, s.J_ptr[e], s.J_ptr[e + 1])
+        acc = isJ ? sum_list<R>(sc, s.J_list, s.J_ptr[ej], s.J_ptr[ej + 1])
                   : sum_list<R>(sc, s.f_list, s.f_ptr[i], s.f_ptr[i + 1]);
     }
     if (hom_on) {

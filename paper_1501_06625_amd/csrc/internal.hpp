@@ -37,8 +37,9 @@ struct SysView {
     const int32_t *f_list;
     const int32_t *J_ptr;
     const int32_t *J_list;
-    // J_list interleaved per wavefront of 64 entries (or NULL): entry c of
-    // the list of e at J_ilv[J_wbase[e / 64] + 64 c + e % 64]
+    // J_list in the summation's lane order (lane q = i n + k takes entry
+    // e = k N + i) interleaved per wavefront of 64 lanes (or NULL): entry c
+    // of the list of lane q at J_ilv[J_wbase[q / 64] + 64 c + q % 64]
     const int32_t *J_wbase;
     const int32_t *J_ilv;
     const int32_t *deg;
