@@ -45,11 +45,11 @@ FP64_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 # bytes); valid for the kernels as they are now (summary and commands:
 # profiles/newton_step_dense32_dd_b10240.md)
 HBM_COUNTERS_KIB = {
-    "mgs": {(8, 0): (945157.6, 5453032.7), (8, 1): (274861.6, 205512.0), (8, 2): (275001.8, 206140.7),
-            (8, 3): (437254.4, 542531.0), (16, 0): (885618.4, 4779626.7), (16, 1): (274882.0, 205953.5),
-            (16, 2): (275021.1, 205777.8), (16, 3): (452625.2, 540710.9), (32, 0): (784480.7, 3993257.2),
-            (32, 1): (274894.0, 208023.4), (32, 3): (480647.3, 537131.4)},
-    "eval_monomials": (38058.0, 5570560.0), "eval_sums": (4441688.5, 339787.0)}
+    "mgs": {(8, 0): (944562.9, 5452785.8), (8, 1): (274861.8, 205510.5), (8, 2): (275001.7, 206138.1),
+            (8, 3): (437229.4, 542433.9), (16, 0): (893912.3, 4792419.1), (16, 1): (274882.1, 205929.2),
+            (16, 2): (275020.9, 205765.6), (16, 3): (448803.9, 540816.6), (32, 0): (786243.4, 3997342.1),
+            (32, 1): (274893.8, 208196.9), (32, 3): (477702.4, 537157.2)},
+    "eval_monomials": (37602.3, 5570560.0), "eval_sums": (3649021.3, 393744.9)}
 MGS_PIN = None  # (lane group, storage) from --mgs-group / --mgs-storage, else autotuned
 FETCH_CAL, WRITE_CAL = 10485760 / (5131.5 * 1024), 1.0
 _T0 = time.time()
