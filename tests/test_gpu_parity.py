@@ -859,6 +859,29 @@ def test_batch_persistent_bitwise(H, P):
         assert rg == rp and _bitwise_equal(xg, xp)
 
 
+def test_batch_persistent_falls_back_to_graph(H):
+    """A persistent batch in mixed precision, or with slots on the tiled
+    solve, runs the captured graph: bitwise the results of a batch that never
+    asked for the persistent form."""
+    P = 2
+    cases = _split_cases(P)
+    systems = [H.System(ps) for ps, _, _ in cases]
+    maxs = max(sd.info().nslots for sd in systems)
+    for kw in (dict(mixed=True), dict(split_n=16)):
+        out = {}
+        for persistent in (False, True):
+            bt = H.Batch(P, capacity=len(cases), max_n=40, max_nslots=maxs, max_steps=20,
+                         persistent=persistent, **kw)
+            for slot, ((ps, gam, x0), sd) in enumerate(zip(cases, systems)):
+                bt.add(slot, sd, gam, dev(x0))
+            bt.run()
+            out[persistent] = [(host(x), r.tobytes()) for x, r in
+                               (bt.result(slot, ps.n) for slot, (ps, _, _) in enumerate(cases))]
+            bt.free()
+        for (xa, ra), (xb, rb) in zip(out[False], out[True]):
+            assert ra == rb and _bitwise_equal(xa, xb), kw
+
+
 def test_batch_step_by_step_polling(H):
     """Stepping a few steps at a time and polling reports progress."""
     P = 2
