@@ -280,10 +280,11 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
         }
         return group_sum<R, GRP>(s, lane);
     };
-    // column j, just updated by the calling group: r_jj = sqrt(||a_j||^2),
-    // 1/r_jj and q_j = a_j / r_jj on the group's rows; false when singular
-    auto normalise = [&](int j, double *aj) -> bool {
-        const R rkk = sqrt(group0_norm2(aj));
+    // column j, just updated by the calling group, with n2 = ||a_j||^2:
+    // r_jj = sqrt(n2), 1/r_jj and q_j = a_j / r_jj on the group's rows;
+    // false when singular
+    auto normalise = [&](int j, double *aj, const R &n2) -> bool {
+        const R rkk = sqrt(n2);
         if (!(lead(rkk) > 0.0) || !rfinite(rkk)) return false;
         const R iv = div(rmake<R>(1.0), rkk);
         if (lane == 0) {
@@ -302,7 +303,7 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
     __shared__ int s_bad[2];
     if (tid < 2) s_bad[tid] = 0;
     __syncthreads();
-    if (g == 0 && !normalise(0, col(0)) && lane == 0) s_bad[0] = 1;
+    if (g == 0 && !normalise(0, col(0), group0_norm2(col(0))) && lane == 0) s_bad[0] = 1;
     __syncthreads();
 
     bool singular = false;
@@ -323,12 +324,28 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
             }
             r = group_csum<R, GRP>(r, lane);
             if (lane == 0) cstore(p.R + ((size_t)j * n + k) * W, r);
+            // look ahead: the group of column k+1 normalises it right away,
+            // in DD and FP64 with its squared norm formed from the updated
+            // values as they are stored (the rows and order of group0_norm2,
+            // so the same bits); QD reads the column again, as the extra
+            // accumulator would cost it registers
+            constexpr bool fused = P != 4;
+            const bool next = j == k + 1 && j < n;
+            R n2 = rmake<R>(0.0);
+            bool first_n2 = true;
             for (int i = lane; i < N; i += GRP) {
                 double *q = aj + (size_t)i * W;
-                cstore(q, csub(cload<R>(q), cmul(r, cload<R>(ak + (size_t)i * W))));
+                const cx<R> u = csub(cload<R>(q), cmul(r, cload<R>(ak + (size_t)i * W)));
+                cstore(q, u);
+                if (fused && next) {
+                    const R v = cnorm2(u);
+                    n2 = first_n2 ? v : add(n2, v);
+                    first_n2 = false;
+                }
             }
-            // look ahead: the group of column k+1 normalises it right away
-            if (j == k + 1 && j < n && !normalise(j, aj) && lane == 0) s_bad[(k + 1) & 1] = 1;
+            if (next && !normalise(j, aj, fused ? group_sum<R, GRP>(n2, lane) : group0_norm2(aj)) &&
+                lane == 0)
+                s_bad[(k + 1) & 1] = 1;
         }
         __syncthreads();
     }
