@@ -45,11 +45,11 @@ FP64_PEAK_TFLOPS = 78.6  # 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 # bytes); valid for the kernels as they are now (summary and commands:
 # profiles/newton_step_dense32_dd_b10240.md)
 HBM_COUNTERS_KIB = {
-    "mgs": {(8, 0): (944562.9, 5452785.8), (8, 1): (274861.8, 205510.5), (8, 2): (275001.7, 206138.1),
-            (8, 3): (437229.4, 542433.9), (16, 0): (893912.3, 4792419.1), (16, 1): (274882.1, 205929.2),
-            (16, 2): (275020.9, 205765.6), (16, 3): (448803.9, 540816.6), (32, 0): (786243.4, 3997342.1),
-            (32, 1): (274893.8, 208196.9), (32, 3): (477702.4, 537157.2)},
-    "eval_monomials": (37602.3, 5570560.0), "eval_sums": (3649021.3, 393744.9)}
+    "mgs": {(8, 0): (914308.5, 5363301.7), (8, 1): (274850.0, 205529.5), (8, 2): (274997.6, 206119.3),
+            (8, 3): (437086.8, 542545.7), (16, 0): (876101.0, 4627639.1), (16, 1): (274880.8, 205993.9),
+            (16, 2): (275024.4, 205809.6), (16, 3): (451486.8, 540727.1), (32, 0): (793216.0, 3988355.4),
+            (32, 1): (274887.6, 207304.7), (32, 3): (479989.7, 537147.9)},
+    "eval_monomials": (38055.1, 5570560.0), "eval_sums": (3648677.0, 393871.9)}
 MGS_PIN = None  # (lane group, storage) from --mgs-group / --mgs-storage, else autotuned
 FETCH_CAL, WRITE_CAL = 10485760 / (5131.5 * 1024), 1.0
 _T0 = time.time()
