@@ -5,7 +5,8 @@
 // memory, 1 staged in LDS, 2 held in registers by the owning lane groups,
 // 3 in registers a panel of columns at a time, left-looking), per precision
 // and row count bucket.  hcn_autotune times a Newton step of a given system for every
-// choice (HIP events on the caller's stream) and keeps the fastest; the
+// choice (HIP events on the caller's stream) and keeps, among those within
+// 2 % of the fastest, the one that moves the least memory; the
 // table can be saved to and loaded from a text file (one line per entry:
 // "P Nbucket group lds").  A choice depends only on (P, N), never on what
 // else is in a batch, so a path gives the same bits alone and in a mix.
@@ -15,6 +16,7 @@
 #include <map>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "internal.hpp"
 #include "mgs_common.hpp"
@@ -115,8 +117,9 @@ int hcn_tune_load(const char *path) {
 extern "C" {
 
 // Time hcn_newton_step of `sys` at the B points x_dev ([B][n][2][P], not
-// modified) for every lane-group width and LDS staging choice, and keep the
-// fastest in the table for (P, N).  Outputs the choice and its time.
+// modified) for every lane-group width and storage choice, and keep in the
+// table for (P, N) the one that moves the least memory among those within
+// 2 % of the fastest.  Outputs the choice and its time.
 int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_group,
                  int *best_lds, double *best_ms, void *stream) {
     if (!sys || !x_dev || B < 1 || reps < 1) return HCN_EINVAL;
@@ -144,6 +147,11 @@ int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_gr
     const int prev_group = tune_mgs_group(P, N), prev_lds = tune_mgs_lds(P, N);
     int bg = prev_group, bl = prev_lds, rc = HCN_OK;
     double bms = 1e300;
+    struct Timed {
+        int grp, lds;
+        double ms;
+    };
+    std::vector<Timed> timed;
     const bool lds_fits = mgs_lds_bytes(N, n, P) <= mgs_lds_limit();
     for (int grp : {8, 16, 32}) {
         int rpl = 0, cpg = 0;
@@ -165,11 +173,27 @@ int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_gr
                 (void)hipEventElapsedTime(&ms, e0, e1);
             }
             if (rc) break;
-            if (ms / reps < bms) {
-                bms = ms / reps;
-                bg = grp;
-                bl = lds;
-            }
+            timed.push_back({grp, lds, ms / reps});
+            bms = std::min(bms, (double)ms / reps);
+        }
+    }
+    // among the choices within 2 % of the fastest (timing noise), keep the
+    // one that moves the least memory: [A | b] in LDS, then in registers,
+    // then panels in registers, then global memory (whose in-place column
+    // updates reach HBM); the fastest first within each storage
+    {
+        const int rank[4] = {3, 0, 1, 2};  // storage 0..3
+        const Timed *pick = nullptr;
+        for (const Timed &t : timed) {
+            if (t.ms > 1.02 * bms) continue;
+            if (!pick || rank[t.lds] < rank[pick->lds] ||
+                (rank[t.lds] == rank[pick->lds] && t.ms < pick->ms))
+                pick = &t;
+        }
+        if (pick) {
+            bg = pick->grp;
+            bl = pick->lds;
+            bms = pick->ms;
         }
     }
     tune_set(P, N, rc ? prev_group : bg, rc ? prev_lds : bl);
