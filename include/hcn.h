@@ -198,9 +198,10 @@ int hcn_tune_load(const char *path);
 /* Autotuner: times hcn_newton_step of `sys` at the B points x_dev (device
  * [B][n][2][P], left unchanged) for every lane-group width and storage choice
  * (reps steps each after a warm-up pass, HIP events on `stream`), stores the
- * choice in the table for (P, N) and returns it with its time: among the
- * choices within 2 % of the fastest, the one that moves the least memory
- * (LDS, then registers, then panels, then global memory).  Synchronous. */
+ * choice in the table for (P, N) and returns it with its time: the fastest,
+ * or [A | b] staged in LDS when that is within 5 % of the fastest and fits
+ * every row count of the bucket (it moves a tenth of the global-memory
+ * form's HBM traffic).  Synchronous. */
 int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_group,
                  int *best_lds, double *best_ms, void *stream);
 

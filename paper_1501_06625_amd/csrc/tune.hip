@@ -5,8 +5,8 @@
 // memory, 1 staged in LDS, 2 held in registers by the owning lane groups,
 // 3 in registers a panel of columns at a time, left-looking), per precision
 // and row count bucket.  hcn_autotune times a Newton step of a given system for every
-// choice (HIP events on the caller's stream) and keeps, among those within
-// 2 % of the fastest, the one that moves the least memory; the
+// choice (HIP events on the caller's stream) and keeps the fastest, or [A | b]
+// staged in LDS when that is within 5 % of it and fits the whole bucket; the
 // table can be saved to and loaded from a text file (one line per entry:
 // "P Nbucket group lds").  A choice depends only on (P, N), never on what
 // else is in a batch, so a path gives the same bits alone and in a mix.
@@ -118,8 +118,9 @@ extern "C" {
 
 // Time hcn_newton_step of `sys` at the B points x_dev ([B][n][2][P], not
 // modified) for every lane-group width and storage choice, and keep in the
-// table for (P, N) the one that moves the least memory among those within
-// 2 % of the fastest.  Outputs the choice and its time.
+// table for (P, N) the fastest, or LDS staging when it is within 5 % of the
+// fastest and fits every row count of the bucket.  Outputs the choice and
+// its time.
 int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_group,
                  int *best_lds, double *best_ms, void *stream) {
     if (!sys || !x_dev || B < 1 || reps < 1) return HCN_EINVAL;
@@ -177,19 +178,20 @@ int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_gr
             bms = std::min(bms, (double)ms / reps);
         }
     }
-    // among the choices within 2 % of the fastest (timing noise), keep the
-    // one that moves the least memory: [A | b] in LDS, then in registers,
-    // then panels in registers, then global memory (whose in-place column
-    // updates reach HBM); the fastest first within each storage
+    // among the choices within 5 % of the fastest (run-to-run noise of the
+    // timings, and under 2 % of a Newton step for the solve), keep [A | b]
+    // staged in LDS when that fits every row count of the bucket: the
+    // global-memory form's in-place column updates reach HBM.  Otherwise
+    // the fastest.
     {
-        const int rank[4] = {3, 0, 1, 2};  // storage 0..3
-        const Timed *pick = nullptr;
+        const int Nb = nbucket(N);
+        const bool bucket_fits = mgs_lds_bytes(Nb, Nb, P) <= mgs_lds_limit();
+        const Timed *fastest = nullptr, *staged = nullptr;
         for (const Timed &t : timed) {
-            if (t.ms > 1.02 * bms) continue;
-            if (!pick || rank[t.lds] < rank[pick->lds] ||
-                (rank[t.lds] == rank[pick->lds] && t.ms < pick->ms))
-                pick = &t;
+            if (!fastest || t.ms < fastest->ms) fastest = &t;
+            if (bucket_fits && t.lds == 1 && (!staged || t.ms < staged->ms)) staged = &t;
         }
+        const Timed *pick = (staged && staged->ms <= 1.05 * bms) ? staged : fastest;
         if (pick) {
             bg = pick->grp;
             bl = pick->lds;
