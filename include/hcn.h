@@ -12,8 +12,10 @@
  * equation (1) (Fig. 3, equation (4)).
  *
  * Numbers.  A real is P doubles, most significant limb first, the limbs
- * non-overlapping: P = 2 is double-double (DD), P = 4 quad-double (QD).  A
- * complex number is [2][P]: the real limbs, then the imaginary limbs.
+ * non-overlapping: P = 1 is double (D), P = 2 double-double (DD), P = 4
+ * quad-double (QD), the three modes of Section 3.1.  A complex number is
+ * [2][P]: the real limbs, then the imaginary limbs.  The batch, the serving
+ * loop and the mixed-precision corrector take DD and QD.
  *
  * Memory.  Pointers named *_dev are device pointers (hipMalloc or a torch
  * CUDA tensor); everything else is host memory.  Device arrays are
@@ -74,9 +76,15 @@ typedef struct hcn_sys_s *hcn_sys;
  *           monomial, exponent 1..15; a monomial with no pair is a
  *           constant term,
  *   coef    [nmon][2][P] complex coefficients.
- * Requires P in {2, 4}, 1 <= n <= N <= 4096, at most 64 pairs per monomial.
+ * Requires P in {1, 2, 4} and 1 <= n <= N <= 4096 (a monomial has at most n
+ * pairs; those of more than 64 variables are evaluated by a loop form of
+ * the reverse mode).
  * The handle owns its device tables; it is immutable and may be shared by
  * calls on any stream.  Synchronous (returns after the upload). */
+/* hcn_sys_free gives up the caller's reference.  A batch that lists the
+ * system (hcn_batch_add) and a serving request that names it
+ * (hcn_server_submit) hold references of their own, so the device tables
+ * are freed only when the last of them lets go. */
 int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr,
                  const int32_t *mon_ptr, const int32_t *var, const int32_t *exp,
                  const double *coef);
@@ -138,15 +146,12 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A_dev, double *b_dev,
 /* Select the MGS variant used by every solve (process-wide): 0 automatic
  * (2 for large single problems, else 1), 1 one workgroup per problem,
  * 2 right-looking across workgroups (one launch per column step, the
- * trailing matrix re-read every step), 3 column-resident across workgroups
- * (one cooperative launch per problem; each workgroup keeps its columns in
- * LDS), 4 tiled (Section 1: right-looking over panels of T columns, each
- * panel factored by one workgroup with its columns in registers, then one
- * launch applies the panel to every later column, held in registers:
- * 2 ceil(n/T) launches).  Variants 2 and 3 give bitwise identical results;
- * 1 and 4 differ from them only by the rounding of their reductions.
- * 3 falls back to 2 when the columns do not fit in LDS, 4 falls back to 2
- * when N > 512 (DD, FP64) or N > 256 (QD).  EINVAL outside 0..4. */
+ * trailing matrix re-read every step), 4 tiled (Section 1: right-looking
+ * over panels of T columns, each panel factored by one workgroup with its
+ * columns in registers, then one launch applies the panel to every later
+ * column, held in registers: 2 ceil(n/T) launches).  1 and 4 differ from 2
+ * only by the rounding of their reductions.  4 falls back to 2 when
+ * N > 512 (DD, FP64) or N > 256 (QD).  EINVAL outside {0, 1, 2, 4}. */
 int hcn_set_mgs_variant(int variant);
 
 /* Panel width T of variant 4 (process-wide), 1 <= T <= 16; default 16.
@@ -161,6 +166,18 @@ int hcn_set_mgs_panel(int T);
  * normalised inputs; the first avoids running both sides of the branches
  * across a wavefront whose lanes differ in exponents. */
 int hcn_set_mon_uniform(int on);
+
+/* Monomial form of the evaluation with gradients (process-wide; default 0):
+ * 0 the reverse mode, one lane per monomial (Section 3.2, Table 1); 1 the
+ * tree mode of Section 3.2: a group of G lanes (the power of two >= the
+ * most variables in a monomial of the system, at least 4, at most 64) per
+ * monomial forms the product of its factors' powers, the prefix and suffix
+ * products of its variables by log2 G levels of shuffles, and every partial
+ * as prefix x suffix; systems with monomials of more than 64 variables, and
+ * value-only evaluations, keep the reverse mode.  The two forms round
+ * differently (reductions of products in another order); both are within
+ * the stated tolerance of the plain definition. */
+int hcn_set_mon_tree(int on);
 
 /* Point chunking (process-wide) of hcn_newton_step, hcn_newton,
  * hcn_newton_mixed and hcn_track_paths: each Newton iteration runs its
@@ -258,9 +275,11 @@ int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B,
 
 /* ------------------------------------------------------------------------
  * Path tracking (Fig. 3 with the step bounds of equation (4)), the step
- * size controlled on the device: trial t = min(1, t_acc + dt); linear
- * extrapolation through the two last accepted points (constant before the
- * second); Fig. 2 corrector; on success accept and, once more than two
+ * size controlled on the device: trial t = min(1, t_acc + dt); prediction
+ * by the polynomial through the last accepted points (Section 3.1: degree
+ * predictor_order, or one less than the number of points accepted so far,
+ * the start point included; Lagrange form, weights from the double
+ * differences of the t values); Fig. 2 corrector; on success accept and, once more than two
  * successes are counted, double dt up to max_dt; on failure reset the count
  * and halve dt, failing below min_dt; fail after more than max_steps steps.
  * At t = 1 Newton's method refines with end_tol and end_iters.
@@ -271,7 +290,8 @@ typedef struct {
     double tol_res, tol_dx, max_eq_val, max_dt, min_dt;
     int max_steps, end_iters;
     double end_tol;
-    int predictor_order;  /* 0: constant, 1: linear (secant) */
+    int predictor_order;  /* degree of the extrapolation, 0..4 (EINVAL otherwise):
+                             0 constant, 1 secant, up to 4 (Section 4.2) */
 } hcn_track_params;
 
 typedef struct {

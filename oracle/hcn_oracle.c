@@ -375,7 +375,9 @@ static rr r_from_d(double d)
 static rr r_add(int P, rr a, rr b)
 {
     rr z = r_zero();
-    if (P == 2)
+    if (P == 1)
+        z.v[0] = a.v[0] + b.v[0];
+    else if (P == 2)
         dd_add(a.v, b.v, z.v);
     else
         qd_add(a.v, b.v, z.v);
@@ -398,7 +400,9 @@ static rr r_sub(int P, rr a, rr b)
 static rr r_mul(int P, rr a, rr b)
 {
     rr z = r_zero();
-    if (P == 2)
+    if (P == 1)
+        z.v[0] = a.v[0] * b.v[0];
+    else if (P == 2)
         dd_mul(a.v, b.v, z.v);
     else
         qd_mul(a.v, b.v, z.v);
@@ -408,7 +412,9 @@ static rr r_mul(int P, rr a, rr b)
 static rr r_mul_d(int P, rr a, double d)
 {
     rr z = r_zero();
-    if (P == 2)
+    if (P == 1)
+        z.v[0] = a.v[0] * d;
+    else if (P == 2)
         dd_mul_d(a.v, d, z.v);
     else
         qd_mul_d(a.v, d, z.v);
@@ -418,7 +424,9 @@ static rr r_mul_d(int P, rr a, double d)
 static rr r_div(int P, rr a, rr b)
 {
     rr z = r_zero();
-    if (P == 2)
+    if (P == 1)
+        z.v[0] = a.v[0] / b.v[0];
+    else if (P == 2)
         dd_div(a.v, b.v, z.v);
     else
         qd_div(a.v, b.v, z.v);
@@ -428,7 +436,9 @@ static rr r_div(int P, rr a, rr b)
 static rr r_sqrt(int P, rr a)
 {
     rr z = r_zero();
-    if (P == 2)
+    if (P == 1)
+        z.v[0] = sqrt(a.v[0]);
+    else if (P == 2)
         dd_sqrt(a.v, z.v);
     else
         qd_sqrt(a.v, z.v);
@@ -584,7 +594,7 @@ int ora_elementwise(int op, int P, int count, const double *a, const double *b,
                     double *out)
 {
     int q;
-    if (P != 2 && P != 4 && op < 20)
+    if (P != 1 && P != 2 && P != 4 && op < 20)
         return ORA_EINVAL;
     for (q = 0; q < count; q++) {
         switch (op) {
@@ -656,7 +666,7 @@ int ora_eval(const ora_sys *S, const double *x, double *f, double *J)
     const size_t W = 2 * (size_t)P;
     int i, m, q, r, e;
     cc *xs;
-    if (P != 2 && P != 4)
+    if (P != 1 && P != 2 && P != 4)
         return ORA_EINVAL;
     xs = (cc *)malloc(sizeof(cc) * (size_t)(n > 0 ? n : 1));
     if (!xs)
@@ -774,7 +784,7 @@ int ora_mgs_solve(int P, int N, int n, double *A, double *b, double *dx, double 
     int i, j, k;
     rr *inv;
     cc *Rl;
-    if ((P != 2 && P != 4) || n < 1 || N < n)
+    if ((P != 1 && P != 2 && P != 4) || n < 1 || N < n)
         return ORA_EINVAL;
     inv = (rr *)malloc(sizeof(rr) * (size_t)n);
     Rl = (cc *)malloc(sizeof(cc) * (size_t)(n + 1) * n);
@@ -829,7 +839,8 @@ int ora_mgs_solve(int P, int N, int n, double *A, double *b, double *dx, double 
 }
 
 /* ======================================================================
- * Newton's method (Fig. 2) and the path tracker (Fig. 3)
+ * the corrector (Section 2, equations (2) and (3); Fig. 2) and the
+ * increment-and-fix tracker (equation (4); Fig. 3)
  * ==================================================================== */
 
 typedef struct {
@@ -844,54 +855,119 @@ typedef struct {
     double dx_norm;   /* last update norm, 0 if none */
 } ora_newton_result;
 
-/* Fig. 2: for up to max_iter iterations evaluate, take the residual norm,
- * fail if it grew beyond the previous one (initially max_eq_val), succeed if
- * it is below tol_res, else solve J dx = -h, update x, succeed if the update
- * norm is below tol_dx.  Norms are infinity norms of the leading limbs. */
+/* What the corrector does next. */
+typedef enum { CORR_EVALUATE, CORR_SOLVE, CORR_STOP } corr_phase;
+
+/* Verdict on a residual norm r when the previous accepted residual (or
+ * max_eq_val before the first) is `ceiling`: NaN stops, growth beyond the
+ * ceiling is divergence, a residual under the tolerance is convergence;
+ * -1 means keep going.  Norms are infinity norms of the leading limbs,
+ * taken in double (the magnitude is all that matters). */
+static int judge_residual(double r, double ceiling, double tol)
+{
+    if (r != r)
+        return ORA_NAN;
+    if (r > ceiling)
+        return ORA_DIVERGED;
+    if (r < tol)
+        return ORA_OK;
+    return -1;
+}
+
+/* Verdict on the size d of the update just applied. */
+static int judge_update(double d, double tol)
+{
+    if (d != d)
+        return ORA_NAN;
+    if (d < tol)
+        return ORA_OK;
+    return -1;
+}
+
+/* Newton's method as a small machine with two phases.  EVALUATE forms the
+ * residual h and the Jacobian at z and judges the residual (equation (3),
+ * the backward error); SOLVE finds dz from J dz = -h, adds it to z and
+ * judges the update (the forward error).  The residual of an iteration may
+ * not exceed the one before it, which starts at max_eq_val.  Either test
+ * ends the corrector with success; running out of evaluations ends it
+ * unconverged. */
 int ora_newton(const ora_sys *F, const ora_sys *G, const double *gamma,
-               int relax_k, double t, double *x, const ora_newton_params *prm,
+               int relax_k, double t, double *z, const ora_newton_params *prm,
                ora_newton_result *res)
 {
     const int P = F->P, N = F->N, n = F->n;
     const size_t W = 2 * (size_t)P;
-    double *h, *J, *dx, last = prm->max_eq_val;
-    int it, rc = ORA_NOT_CONVERGED, q;
+    double *h, *J, *dz, ceiling = prm->max_eq_val, r_now = 0.0;
+    int verdict = ORA_NOT_CONVERGED, q;
+    corr_phase phase = CORR_EVALUATE;
     res->iters = 0;
     res->res_norm = 0.0;
     res->dx_norm = 0.0;
     h = (double *)malloc(sizeof(double) * (size_t)N * W);
     J = (double *)malloc(sizeof(double) * (size_t)N * n * W);
-    dx = (double *)malloc(sizeof(double) * (size_t)n * W);
-    if (!h || !J || !dx) {
-        free(h); free(J); free(dx);
+    dz = (double *)malloc(sizeof(double) * (size_t)n * W);
+    if (!h || !J || !dz) {
+        free(h); free(J); free(dz);
         return res->status = ORA_ENOMEM;
     }
-    for (it = 0; it < prm->max_iter; it++) {
-        double rn, dn;
-        int e = ora_eval_h(F, G, gamma, relax_k, t, x, h, J);
-        if (e) { rc = e; break; }
-        res->iters++;
-        rn = lead_norm(P, N, h);
-        res->res_norm = rn;
-        if (rn != rn) { rc = ORA_NAN; break; }
-        if (rn > last) { rc = ORA_DIVERGED; break; }
-        if (rn < prm->tol_res) { rc = ORA_OK; break; }
-        for (q = 0; q < N; q++)
-            c_store(P, c_neg(P, c_load(P, h + q * W)), h + q * W);
-        e = ora_mgs_solve(P, N, n, J, h, dx, NULL);
-        if (e) { rc = e; break; }
-        dn = lead_norm(P, n, dx);
-        res->dx_norm = dn;
-        if (dn != dn) { rc = ORA_NAN; break; }
-        for (q = 0; q < n; q++)
-            c_store(P, c_add(P, c_load(P, x + q * W), c_load(P, dx + q * W)), x + q * W);
-        if (dn < prm->tol_dx) { rc = ORA_OK; break; }
-        last = rn;
+    while (phase != CORR_STOP) {
+        if (phase == CORR_EVALUATE) {
+            int e, v;
+            if (res->iters >= prm->max_iter) {
+                verdict = ORA_NOT_CONVERGED;
+                phase = CORR_STOP;
+                continue;
+            }
+            e = ora_eval_h(F, G, gamma, relax_k, t, z, h, J);
+            if (e) {
+                verdict = e;
+                phase = CORR_STOP;
+                continue;
+            }
+            res->iters++;
+            r_now = lead_norm(P, N, h);
+            res->res_norm = r_now;
+            v = judge_residual(r_now, ceiling, prm->tol_res);
+            if (v >= 0) {
+                verdict = v;
+                phase = CORR_STOP;
+            } else {
+                phase = CORR_SOLVE;
+            }
+        } else {
+            double d;
+            int e, v;
+            for (q = 0; q < N; q++)
+                c_store(P, c_neg(P, c_load(P, h + q * W)), h + q * W);
+            e = ora_mgs_solve(P, N, n, J, h, dz, NULL);
+            if (e) {
+                verdict = e;
+                phase = CORR_STOP;
+                continue;
+            }
+            d = lead_norm(P, n, dz);
+            res->dx_norm = d;
+            if (d != d) {
+                verdict = ORA_NAN;  /* z is left as it was */
+                phase = CORR_STOP;
+                continue;
+            }
+            for (q = 0; q < n; q++)
+                c_store(P, c_add(P, c_load(P, z + q * W), c_load(P, dz + q * W)), z + q * W);
+            v = judge_update(d, prm->tol_dx);
+            if (v >= 0) {
+                verdict = v;
+                phase = CORR_STOP;
+            } else {
+                ceiling = r_now;
+                phase = CORR_EVALUATE;
+            }
+        }
     }
     free(h);
     free(J);
-    free(dx);
-    return res->status = rc;
+    free(dz);
+    return res->status = verdict;
 }
 
 /* one Newton iteration without tests: evaluate, solve, update.  norms[0] =
@@ -928,6 +1004,54 @@ int ora_newton_step(const ora_sys *F, const ora_sys *G, const double *gamma,
     return e;
 }
 
+#define ORA_MAX_ORDER 4
+
+/* The predictor of Section 3.1: the polynomial of degree d through the
+ * points (ts[j], xs[j]), j = 0..d, evaluated at t, coordinate by
+ * coordinate, in Lagrange form: x(t) = sum_j w_j xs[j] with
+ * w_j = prod_{m != j} (t - ts[m]) / prod_{m != j} (ts[j] - ts[m]).
+ * Each weight is its numerator product (m ascending) over its denominator
+ * product, in the working precision from the double differences; the sum
+ * runs over j ascending.  d = 0 copies xs[0].  xs: [d+1][n][2][P]. */
+int ora_predict(int P, int n, int d, const double *ts, const double *xs, double t,
+                double *out)
+{
+    const size_t W = 2 * (size_t)P;
+    rr w[ORA_MAX_ORDER + 1];
+    int i, j, m;
+    if ((P != 1 && P != 2 && P != 4) || n < 0 || d < 0 || d > ORA_MAX_ORDER)
+        return ORA_EINVAL;
+    for (j = 0; j <= d; j++) {
+        rr num = r_from_d(1.0), den = r_from_d(1.0);
+        int first = 1;
+        for (m = 0; m <= d; m++) {
+            if (m == j)
+                continue;
+            if (first) {
+                num = r_from_d(t - ts[m]);
+                den = r_from_d(ts[j] - ts[m]);
+                first = 0;
+            } else {
+                num = r_mul(P, num, r_from_d(t - ts[m]));
+                den = r_mul(P, den, r_from_d(ts[j] - ts[m]));
+            }
+        }
+        w[j] = d == 0 ? r_from_d(1.0) : r_div(P, num, den);
+    }
+    for (i = 0; i < n; i++) {
+        cc acc;
+        if (d == 0) {
+            acc = c_load(P, xs + (size_t)i * W);
+        } else {
+            acc = c_scale(P, w[0], c_load(P, xs + (size_t)i * W));
+            for (j = 1; j <= d; j++)
+                acc = c_add(P, acc, c_scale(P, w[j], c_load(P, xs + ((size_t)j * n + i) * W)));
+        }
+        c_store(P, acc, out + (size_t)i * W);
+    }
+    return ORA_OK;
+}
+
 typedef struct {
     int max_iter;
     double tol_res, tol_dx, max_eq_val, max_dt, min_dt;
@@ -941,114 +1065,150 @@ typedef struct {
     double t, res_norm, dx_norm;
 } ora_path_result;
 
-/* Fig. 3 with the step bounds of equation (4): t_acc = 0, dt = max_dt;
- * while t_acc < 1: stop when more than max_steps steps were taken; trial
- * t = min(1, t_acc + dt); predict; correct (Fig. 2); on success accept
- * (t, x), count it and once more than two successes are counted double dt
- * up to max_dt; on failure reset the count and halve dt, stopping when dt
- * drops below min_dt; count the step.  The predictor extrapolates linearly
- * through the two last accepted points (constant before the second point).
- * At t = 1 Newton's method refines with end_tol and end_iters. */
-int ora_track(const ora_sys *F, const ora_sys *G, const double *gamma,
-              int relax_k, const double *x0, const ora_track_params *prm,
-              double *x_out, ora_path_result *out)
+/* What the tracker does next. */
+typedef enum { TRK_ADVANCE, TRK_PREDICT_CORRECT, TRK_REFINE, TRK_DONE } trk_phase;
+
+/* Increment-and-fix continuation of the homotopy (equation (1)) along one
+ * path, with the step bounds of equation (4), as a machine:
+ *   ADVANCE: give up once more than max_steps steps were taken; otherwise
+ *     the trial parameter is the last accepted t plus dt, clipped at 1;
+ *   PREDICT_CORRECT: extrapolate the path to the trial t through the last
+ *     accepted points (Section 3.1: degree up to predictor_order, one less
+ *     than the points known) and correct with Newton's method.  Success
+ *     accepts the point and counts a success; once the run of successes is
+ *     longer than two, each further success doubles dt up to max_dt.
+ *     Failure ends the run (count 0) and halves dt; below min_dt the path
+ *     is given up.  Either way one step is counted.  Accepting t = 1 moves
+ *     on to REFINE;
+ *   REFINE: Newton's method at t = 1 with end_tol and end_iters.
+ * Readings of the paper: a failed step leaves the accepted (t, x) in place
+ * and the next trial starts from it; a NaN residual or update ends the
+ * path.  trace (optional, trace_cap rows of 4 doubles): per step the trial
+ * t, the dt that produced it, 1 for accepted / 0 for rejected, and the
+ * corrector's evaluations. */
+int ora_track_trace(const ora_sys *F, const ora_sys *G, const double *gamma,
+                    int relax_k, const double *x0, const ora_track_params *prm,
+                    double *x_out, ora_path_result *out, double *trace, int trace_cap)
 {
     const int P = F->P, n = F->n;
     const size_t W = 2 * (size_t)P;
-    double t_acc = 0.0, t_prev = 0.0, dt = prm->max_dt;
-    double *x_acc, *x_prev, *x;
-    int nsucc = 0, have_prev = 0, status = ORA_OK, q;
+    const size_t xb = sizeof(double) * (size_t)n * W;
+    const int order = prm->predictor_order < 0 ? 0
+                    : prm->predictor_order > ORA_MAX_ORDER ? ORA_MAX_ORDER : prm->predictor_order;
+    /* the accepted points, newest first: hist_t[j], hist_x + j n W */
+    double hist_t[ORA_MAX_ORDER + 1], *hist_x, *z;
+    double dt = prm->max_dt, t_try = 0.0;
+    int known = 1, run = 0, status = ORA_OK, j;
+    trk_phase phase = TRK_ADVANCE;
     ora_newton_params np;
     ora_newton_result nr;
     memset(out, 0, sizeof *out);
-    x_acc = (double *)malloc(sizeof(double) * (size_t)n * W);
-    x_prev = (double *)malloc(sizeof(double) * (size_t)n * W);
-    x = (double *)malloc(sizeof(double) * (size_t)n * W);
-    if (!x_acc || !x_prev || !x) {
-        free(x_acc); free(x_prev); free(x);
+    if (order > ORA_MAX_ORDER)
+        return out->status = ORA_EINVAL;
+    hist_x = (double *)malloc(xb * (ORA_MAX_ORDER + 1));
+    z = (double *)malloc(xb);
+    if (!hist_x || !z) {
+        free(hist_x); free(z);
         return out->status = ORA_ENOMEM;
     }
-    memcpy(x_acc, x0, sizeof(double) * (size_t)n * W);
+    hist_t[0] = 0.0;
+    memcpy(hist_x, x0, xb);
     np.max_iter = prm->max_iter;
     np.tol_res = prm->tol_res;
     np.tol_dx = prm->tol_dx;
     np.max_eq_val = prm->max_eq_val;
-    while (t_acc < 1.0) {
-        double t;
-        int rc;
-        if (out->steps > prm->max_steps) {
-            status = ORA_MAX_STEPS;
+    while (phase != TRK_DONE) {
+        switch (phase) {
+        case TRK_ADVANCE:
+            if (hist_t[0] >= 1.0) {
+                phase = TRK_REFINE;
+            } else if (out->steps > prm->max_steps) {
+                status = ORA_MAX_STEPS;
+                phase = TRK_DONE;
+            } else {
+                t_try = hist_t[0] + dt;
+                if (t_try > 1.0)
+                    t_try = 1.0;
+                phase = TRK_PREDICT_CORRECT;
+            }
             break;
-        }
-        t = t_acc + dt;
-        if (t > 1.0)
-            t = 1.0;
-        if (have_prev && prm->predictor_order >= 1) {
-            rr num = r_from_d(t - t_acc), den = r_from_d(t_acc - t_prev);
-            rr ratio = r_div(P, num, den);
-            for (q = 0; q < n; q++) {
-                cc x1 = c_load(P, x_acc + q * W), xp = c_load(P, x_prev + q * W);
-                cc d = c_sub(P, x1, xp);
-                c_store(P, c_add(P, x1, c_scale(P, ratio, d)), x + q * W);
-            }
-        } else {
-            memcpy(x, x_acc, sizeof(double) * (size_t)n * W);
-        }
-        rc = ora_newton(F, G, gamma, relax_k, t, x, &np, &nr);
-        out->newton_iters += nr.iters;
-        out->res_norm = nr.res_norm;
-        out->dx_norm = nr.dx_norm;
-        if (rc == ORA_NAN || rc == ORA_EINVAL || rc == ORA_ENOMEM) {
-            status = rc;
-            out->steps++;
-            break;
-        }
-        if (rc == ORA_OK) {
-            memcpy(x_prev, x_acc, sizeof(double) * (size_t)n * W);
-            t_prev = t_acc;
-            have_prev = 1;
-            memcpy(x_acc, x, sizeof(double) * (size_t)n * W);
-            t_acc = t;
-            out->accepted++;
-            nsucc++;
-            if (nsucc > 2) {
-                dt = 2.0 * dt;
-                if (dt > prm->max_dt)
-                    dt = prm->max_dt;
-            }
-        } else {
-            nsucc = 0;
-            dt = 0.5 * dt;
-            if (dt < prm->min_dt) {
-                status = ORA_STEP_TOO_SMALL;
-                out->steps++;
-                break;
-            }
-        }
-        out->steps++;
-    }
-    out->t = t_acc;
-    if (status == ORA_OK) {
-        ora_newton_params ep = np;
-        ep.max_iter = prm->end_iters;
-        ep.tol_res = prm->end_tol;
-        ep.tol_dx = prm->end_tol;
-        memcpy(x, x_acc, sizeof(double) * (size_t)n * W);
-        if (prm->end_iters > 0) {
-            ora_newton(F, G, gamma, relax_k, 1.0, x, &ep, &nr);
-            out->end_iters = nr.iters;
-            out->end_status = nr.status;
+        case TRK_PREDICT_CORRECT: {
+            const int deg = known - 1 < order ? known - 1 : order;
+            int rc, accepted;
+            ora_predict(P, n, deg, hist_t, hist_x, t_try, z);
+            rc = ora_newton(F, G, gamma, relax_k, t_try, z, &np, &nr);
+            out->newton_iters += nr.iters;
             out->res_norm = nr.res_norm;
             out->dx_norm = nr.dx_norm;
+            accepted = rc == ORA_OK;
+            if (trace && out->steps < trace_cap) {
+                double *row = trace + 4 * (size_t)out->steps;
+                row[0] = t_try;
+                row[1] = dt;
+                row[2] = accepted;
+                row[3] = nr.iters;
+            }
+            out->steps++;
+            if (rc == ORA_NAN || rc == ORA_EINVAL || rc == ORA_ENOMEM) {
+                status = rc;
+                phase = TRK_DONE;
+                break;
+            }
+            if (accepted) {
+                for (j = ORA_MAX_ORDER; j > 0; j--) {
+                    hist_t[j] = hist_t[j - 1];
+                    memcpy(hist_x + (size_t)j * n * W, hist_x + (size_t)(j - 1) * n * W, xb);
+                }
+                hist_t[0] = t_try;
+                memcpy(hist_x, z, xb);
+                if (known < ORA_MAX_ORDER + 1)
+                    known++;
+                out->accepted++;
+                run++;
+                if (run > 2)
+                    dt = 2.0 * dt > prm->max_dt ? prm->max_dt : 2.0 * dt;
+                phase = TRK_ADVANCE;
+            } else {
+                run = 0;
+                dt = 0.5 * dt;
+                phase = dt < prm->min_dt ? TRK_DONE : TRK_ADVANCE;
+                if (phase == TRK_DONE)
+                    status = ORA_STEP_TOO_SMALL;
+            }
+            break;
         }
-        memcpy(x_out, x, sizeof(double) * (size_t)n * W);
-    } else {
-        memcpy(x_out, x_acc, sizeof(double) * (size_t)n * W);
+        case TRK_REFINE:
+            memcpy(z, hist_x, xb);
+            if (prm->end_iters > 0) {
+                ora_newton_params ep = np;
+                ep.max_iter = prm->end_iters;
+                ep.tol_res = prm->end_tol;
+                ep.tol_dx = prm->end_tol;
+                ora_newton(F, G, gamma, relax_k, 1.0, z, &ep, &nr);
+                out->end_iters = nr.iters;
+                out->end_status = nr.status;
+                out->res_norm = nr.res_norm;
+                out->dx_norm = nr.dx_norm;
+            }
+            phase = TRK_DONE;
+            break;
+        default:
+            phase = TRK_DONE;
+            break;
+        }
     }
-    free(x_acc);
-    free(x_prev);
-    free(x);
+    out->t = hist_t[0];
+    memcpy(x_out, status == ORA_OK ? z : hist_x, xb);
+    free(hist_x);
+    free(z);
     return out->status = status;
+}
+
+int ora_track(const ora_sys *F, const ora_sys *G, const double *gamma,
+              int relax_k, const double *x0, const ora_track_params *prm,
+              double *x_out, ora_path_result *out)
+{
+    return ora_track_trace(F, G, gamma, relax_k, x0, prm, x_out, out, NULL, 0);
 }
 
 /* accurate sum helper exposed for tests: sum of count reals in order */

@@ -87,6 +87,10 @@ def lib():
         _lib.ora_newton_step.argtypes = [ctypes.POINTER(_Sys), ctypes.POINTER(_Sys), vp, ci, cd, vp, vp]
         _lib.ora_track.argtypes = [ctypes.POINTER(_Sys), ctypes.POINTER(_Sys), vp, ci, vp,
                                    ctypes.POINTER(_TrackParams), vp, ctypes.POINTER(_PathResult)]
+        _lib.ora_track_trace.argtypes = [ctypes.POINTER(_Sys), ctypes.POINTER(_Sys), vp, ci, vp,
+                                         ctypes.POINTER(_TrackParams), vp,
+                                         ctypes.POINTER(_PathResult), vp, ci]
+        _lib.ora_predict.argtypes = [ci, ci, ci, vp, vp, cd, vp]
         _lib.ora_sum.argtypes = [ci, ci, vp, vp]
     return _lib
 
@@ -215,12 +219,31 @@ DEFAULT_TRACK = dict(max_iter=3, tol_res=1e-12, tol_dx=1e-12, max_eq_val=1.0,
                      end_iters=10, end_tol=None, predictor_order=1)
 
 
-def track(F, G, gamma, k: int, x0: np.ndarray, **kw):
+END_TOL = {1: 1e-14, 2: 1e-28, 4: 1e-58}
+
+
+def predict(P: int, ts, xs: np.ndarray, t: float) -> np.ndarray:
+    """The predictor: the interpolating polynomial of degree len(ts) - 1
+    through (ts[j], xs[j]) at t; xs [d+1][n][2][P], newest first."""
+    ts = np.ascontiguousarray(ts, dtype=np.float64)
+    xs = np.ascontiguousarray(xs, dtype=np.float64)
+    d = ts.size - 1
+    n = xs.shape[1]
+    out = np.zeros((n, 2, P))
+    rc = lib().ora_predict(P, n, d, _p(ts), _p(xs), float(t), _p(out))
+    if rc:
+        raise ValueError(f"ora_predict rc={rc}")
+    return out
+
+
+def track(F, G, gamma, k: int, x0: np.ndarray, trace: bool = False, **kw):
+    """Track one path (Fig. 3).  trace=True also returns the per-step rows
+    (trial t, dt, accepted, corrector evaluations) as a third value."""
     rf, rg = _ref(F), _ref(G)
     p = dict(DEFAULT_TRACK)
     p.update(kw)
     if p["end_tol"] is None:
-        p["end_tol"] = 1e-28 if rf.P == 2 else 1e-58
+        p["end_tol"] = END_TOL[rf.P]
     prm = _TrackParams(int(p["max_iter"]), float(p["tol_res"]), float(p["tol_dx"]),
                        float(p["max_eq_val"]), float(p["max_dt"]), float(p["min_dt"]),
                        int(p["max_steps"]), int(p["end_iters"]), float(p["end_tol"]),
@@ -229,12 +252,17 @@ def track(F, G, gamma, k: int, x0: np.ndarray, **kw):
     gam = np.ascontiguousarray(gamma, dtype=np.float64)
     xo = np.zeros_like(x0)
     out = _PathResult()
-    lib().ora_track(_sp(rf), _sp(rg), _p(gam), int(k), _p(x0), ctypes.byref(prm), _p(xo),
-                    ctypes.byref(out))
-    return xo, SimpleNamespace(status=out.status, steps=out.steps, newton_iters=out.newton_iters,
-                               end_iters=out.end_iters, end_status=out.end_status,
-                               accepted=out.accepted, t=out.t, res_norm=out.res_norm,
-                               dx_norm=out.dx_norm)
+    cap = int(p["max_steps"]) + 2 if trace else 0
+    rows = np.zeros((max(cap, 1), 4))
+    lib().ora_track_trace(_sp(rf), _sp(rg), _p(gam), int(k), _p(x0), ctypes.byref(prm), _p(xo),
+                          ctypes.byref(out), _p(rows) if trace else None, cap)
+    r = SimpleNamespace(status=out.status, steps=out.steps, newton_iters=out.newton_iters,
+                        end_iters=out.end_iters, end_status=out.end_status,
+                        accepted=out.accepted, t=out.t, res_norm=out.res_norm,
+                        dx_norm=out.dx_norm)
+    if trace:
+        return xo, r, rows[:min(out.steps, cap)]
+    return xo, r
 
 
 def total_degree_start(F):

@@ -26,6 +26,7 @@
 #include "mgs_tiled.hpp"
 #include "mp.hpp"
 #include "prof.hpp"
+#include "registry.hpp"
 #include "track_body.hpp"
 
 namespace hcn {
@@ -37,6 +38,7 @@ struct BatchDev {
     const int *slot_sys;  // [cap] registry index, -1 empty
     const int *slot_lds;  // [cap] stage [A | b] in LDS
     double *x, *x_acc, *x_prev, *x_out, *sc, *J, *R, *inv, *dx, *np, *t, *gamma;
+    double *x_old;        // [cap][3][xs] older accepted points (NULL: predictor order <= 1)
     PathState *st;
     hcn_path_result *res;
     int *sing;            // [cap] singular column seen by the tiled MGS
@@ -52,6 +54,8 @@ HCN_DEV TrackPath slot_path(const BatchDev &d, int slot) {
     p.x_acc = d.x_acc + (size_t)slot * d.xs;
     p.x_prev = d.x_prev + (size_t)slot * d.xs;
     p.x_out = d.x_out + (size_t)slot * d.xs;
+    p.old_stride = d.xs;
+    p.x_old = d.x_old ? d.x_old + (size_t)slot * (MAX_PREDICTOR_ORDER - 1) * d.xs : nullptr;
     p.t = d.t + slot;
     p.res = d.res + slot;
     return p;
@@ -90,7 +94,10 @@ __global__ __launch_bounds__(256) void k_b_mon(BatchDev d, const int2 *work) {
     const PointView pv{xb, 2 * d.P, d.P, table ? pows : nullptr};
     const int m = w.y * 256 + threadIdx.x;
     if (m >= s.nmon) return;
-    mon_one<R, KB, MODE, UNI>(s, m, pv, d.sc + (size_t)slot * d.scs);
+    if constexpr (KB == 0)
+        mon_one_long<R, MODE, UNI>(s, m, pv, d.sc + (size_t)slot * d.scs);
+    else
+        mon_one<R, KB, MODE, UNI>(s, m, pv, d.sc + (size_t)slot * d.scs);
 }
 
 // what a sum launch forms: the full [J | -h] with its norm parts, the
@@ -251,7 +258,12 @@ __global__ __launch_bounds__(MGS_THREADS) void k_b_persist(BatchDev d, const int
             __syncthreads();
             if (d.st[slot].c_active) {
                 const PointView pv{xb, 2 * d.P, d.P, nullptr};
-                for (int m = threadIdx.x; m < s.nmon; m += MGS_THREADS) mon_one<R, 64, MON_FSLOT, false>(s, m, pv, sc);
+                for (int m = threadIdx.x; m < s.nmon; m += MGS_THREADS) {
+                    if (s.mon_k[m] > 64)
+                        mon_one_long<R, MON_FSLOT, false>(s, m, pv, sc);
+                    else
+                        mon_one<R, 64, MON_FSLOT, false>(s, m, pv, sc);
+                }
                 __syncthreads();
                 b_sum_full<R>(d, slot, s, nparts, red);
                 __syncthreads();
@@ -355,7 +367,8 @@ int kbucket_b(int k) {
     if (k <= 8) return 8;
     if (k <= 16) return 16;
     if (k <= 32) return 32;
-    return 64;
+    if (k <= 64) return 64;
+    return 1 << 30;  // the loop form
 }
 
 }  // namespace
@@ -365,8 +378,9 @@ struct hcn_batch_s {
     BatchDev d = {};
     void *dmem = nullptr;
     size_t bytes = 0;
-    // registry
-    std::vector<hcn_sys> systems;
+    // registry: the systems the slots refer to (holding a reference on
+    // each) and their device views, by registry index
+    SysRegistry<hcn_sys> reg{0};
     std::vector<SysView> views;
     SysView *d_sys = nullptr;
     int kb = 4;
@@ -412,7 +426,8 @@ void launch_b_mon_u(hcn_batch_s *b, size_t lds, hipStream_t s) {
         case 8: hipLaunchKernelGGL((k_b_mon<R, 8, MODE, UNI>), g, t, lds, s, d, b->d_mon); break;
         case 16: hipLaunchKernelGGL((k_b_mon<R, 16, MODE, UNI>), g, t, lds, s, d, b->d_mon); break;
         case 32: hipLaunchKernelGGL((k_b_mon<R, 32, ML, UNI>), g, t, lds, s, d, b->d_mon); break;
-        default: hipLaunchKernelGGL((k_b_mon<R, 64, ML, UNI>), g, t, lds, s, d, b->d_mon); break;
+        case 64: hipLaunchKernelGGL((k_b_mon<R, 64, ML, UNI>), g, t, lds, s, d, b->d_mon); break;
+        default: hipLaunchKernelGGL((k_b_mon<R, 0, ML, UNI>), g, t, lds, s, d, b->d_mon); break;
     }
 }
 
@@ -422,8 +437,11 @@ void launch_b_mon(hcn_batch_s *b, hipStream_t s) {
     // its own); the uniform form of the common factor when every system
     // allows it (both forms give the same bits)
     size_t lds = 0;
-    bool uni = !b->views.empty();  // every registered system allows the uniform form
-    for (const SysView &v : b->views) {
+    bool uni = false;  // every registered system allows the uniform form
+    for (int q = 0; q < b->reg.size(); ++q) {
+        if (!b->reg.live(q)) continue;
+        const SysView &v = b->views[q];
+        if (lds == 0 && !uni) uni = true;
         lds = std::max(lds, mon_stage_bytes(v, limbs<R>::P));
         if (!mon_uniform(v, limbs<R>::P)) uni = false;
     }
@@ -647,7 +665,8 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
         max_systems < 1 || relax_k < 1)
         return bfail(HCN_EINVAL, "hcn_batch_create: bad sizes (P 2/4, capacity >= 1, 1 <= max_n <= 1024)");
     if (prm->max_iter < 1 || prm->max_iter > 100 || prm->max_steps < 0 || prm->end_iters < 0 ||
-        !(prm->max_dt > 0.0) || prm->max_dt > 1.0 || !(prm->min_dt > 0.0))
+        !(prm->max_dt > 0.0) || prm->max_dt > 1.0 || !(prm->min_dt > 0.0) ||
+        prm->predictor_order < 0 || prm->predictor_order > MAX_PREDICTOR_ORDER)
         return bfail(HCN_EINVAL, "hcn_batch_create: bad tracking parameters");
     auto *b = new hcn_batch_s;
     b->P = P;
@@ -655,6 +674,7 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
     b->max_n = max_n;
     b->max_nslots = max_nslots;
     b->max_sys = max_systems;
+    b->reg = SysRegistry<hcn_sys>(max_systems);
     const long W = 2 * P;
     const long cap = capacity;
     const long xs = max_n * W;
@@ -679,7 +699,8 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
                  o_ss = take(cap * 4), o_sl = take(cap * 4), o_mon = take(b->mon_cap * sizeof(int2)),
                  o_sum = take(b->sum_cap * sizeof(int2)), o_sumf = take(cap * ((max_n + 255) / 256) * sizeof(int2)),
                  o_slots = take(cap * 4), o_done = take(cap * 4),
-                 o_run = take(4), o_sing = take(cap * 4);
+                 o_run = take(4), o_sing = take(cap * 4),
+                 o_old = prm->predictor_order >= 2 ? take(cap * (MAX_PREDICTOR_ORDER - 1) * xs * 8) : 0;
     b->bytes = off;
     if (hipMalloc(&b->dmem, off) != hipSuccess) {
         delete b;
@@ -695,6 +716,7 @@ int hcn_batch_create(hcn_batch *out, int P, int capacity, int max_n, int max_nsl
     d.x_acc = (double *)(base + o_xa);
     d.x_prev = (double *)(base + o_xp);
     d.x_out = (double *)(base + o_xo);
+    d.x_old = prm->predictor_order >= 2 ? (double *)(base + o_old) : nullptr;
     d.sc = (double *)(base + o_sc);
     d.J = (double *)(base + o_J);
     d.R = (double *)(base + o_R);
@@ -763,6 +785,7 @@ int hcn_batch_destroy(hcn_batch b) {
     (void)hipHostFree(b->h_running);
     (void)hipHostFree(b->h_done);
     (void)hipFree(b->dmem);
+    for (hcn_sys h : b->reg.all()) sys_release(h);
     delete b;
     return HCN_OK;
 }
@@ -775,23 +798,31 @@ int hcn_batch_add(hcn_batch b, int slot, hcn_sys sys, const double *gamma, const
     if (slot < 0 || slot >= b->cap) return bfail(HCN_EINVAL, "hcn_batch_add: slot out of range");
     if (b->slot_sys[slot] >= 0) return bfail(HCN_EINVAL, "hcn_batch_add: slot is occupied");
     hcn_sys_info_t info;
-    hcn_sys_info(sys, &info);
+    if (hcn_sys_info(sys, &info) != HCN_OK) return bfail(HCN_EINVAL, "hcn_batch_add: bad system");
     if (info.P != b->P) return bfail(HCN_EINVAL, "hcn_batch_add: precision differs from the batch");
     if (info.N != info.n) return bfail(HCN_EINVAL, "hcn_batch_add: tracking needs N == n");
     if (info.n > b->max_n || info.nslots > b->max_nslots)
         return bfail(HCN_EINVAL, "hcn_batch_add: system larger than the batch was sized for");
-    int idx = -1;
-    for (size_t q = 0; q < b->systems.size(); ++q)
-        if (b->systems[q] == sys) idx = (int)q;
+    bool fresh = false;
+    int idx = b->reg.acquire(sys, &fresh);
     if (idx < 0) {
-        if ((int)b->systems.size() >= b->max_sys)
-            return bfail(HCN_EINVAL, "hcn_batch_add: too many distinct systems");
-        idx = (int)b->systems.size();
-        b->systems.push_back(sys);
+        // every entry is listed: once the queued work has finished, entries
+        // that no slot uses any more can go
+        if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+            return bfail(HCN_EDEVICE, "hcn_batch_add: sync");
+        for (hcn_sys h : b->reg.collect()) sys_release(h);
+        idx = b->reg.acquire(sys, &fresh);
+        if (idx < 0) return bfail(HCN_EINVAL, "hcn_batch_add: too many distinct systems in the slots");
+    }
+    if (fresh) {
+        sys_retain(sys);
         const SysView v = sys_view(sys);
-        b->views.push_back(v);
-        if (hipMemcpy(b->d_sys + idx, &v, sizeof(SysView), hipMemcpyHostToDevice) != hipSuccess)
+        if ((int)b->views.size() < b->reg.size()) b->views.resize(b->reg.size());
+        b->views[idx] = v;
+        if (hipMemcpy(b->d_sys + idx, &v, sizeof(SysView), hipMemcpyHostToDevice) != hipSuccess) {
+            b->reg.drop(idx);
             return bfail(HCN_EDEVICE, "hcn_batch_add: registry upload failed");
+        }
         b->kb = std::max(b->kb, kbucket_b(v.max_k));
     }
     hipStream_t s = (hipStream_t)stream;
@@ -827,6 +858,8 @@ int hcn_batch_set_persistent(hcn_batch b, int on) {
 
 int hcn_batch_release(hcn_batch b, int slot) {
     if (!b || slot < 0 || slot >= b->cap) return bfail(HCN_EINVAL, "hcn_batch_release: bad slot");
+    if (b->slot_sys[slot] < 0) return HCN_OK;
+    b->reg.drop(b->slot_sys[slot]);
     b->slot_sys[slot] = -1;
     b->dirty = true;
     return HCN_OK;

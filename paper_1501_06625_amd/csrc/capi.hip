@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -74,7 +75,7 @@ struct Workspace {
     }
 };
 
-int g_mgs_variant = 0;  // 0 auto, 1 workgroup per problem, 2 right-looking, 3 column-resident, 4 tiled
+int g_mgs_variant = 0;  // 0 auto, 1 workgroup per problem, 2 right-looking, 4 tiled
 size_t g_chunk_bytes = 0;  // 0: every launch covers the whole batch
 
 // the MGS variant for B problems with n unknowns
@@ -144,15 +145,30 @@ MgsArgs chunk_of(MgsArgs a, int b0, int Bc) {
 
 }  // namespace
 
+// A loaded system.  References: the caller's (from hcn_sys_load, given up
+// by hcn_sys_free) and one per batch registry entry or queued serving
+// request that names it; the device tables are freed with the last one.
 struct hcn_sys_s {
     SysView v;
     void *dmem = nullptr;
     size_t bytes = 0;
     int nnz = 0;
     std::vector<int32_t> deg;
+    std::atomic<int> refs{1};
 };
 
 SysView hcn::sys_view(hcn_sys s) { return s->v; }
+
+void hcn::sys_retain(hcn_sys s) {
+    if (s) s->refs.fetch_add(1);
+}
+
+void hcn::sys_release(hcn_sys s) {
+    if (s && s->refs.fetch_sub(1) == 1) {
+        (void)hipFree(s->dmem);
+        delete s;
+    }
+}
 
 extern "C" {
 
@@ -164,7 +180,7 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
                  const int32_t *var, const int32_t *exp, const double *coef) {
     if (!out) return fail(HCN_EINVAL, "hcn_sys_load: out is NULL");
     *out = nullptr;
-    if (P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_sys_load: P must be 2 or 4, got %d", P);
+    if (P != 1 && P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_sys_load: P must be 1, 2 or 4, got %d", P);
     if (n < 1 || N < n || N > 4096)
         return fail(HCN_EINVAL, "hcn_sys_load: need 1 <= n <= N <= 4096 (N=%d n=%d)", N, n);
     if (!eq_ptr || !mon_ptr || !coef) return fail(HCN_EINVAL, "hcn_sys_load: NULL table");
@@ -177,8 +193,8 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
     int max_k = 0;
     for (int m = 0; m < nmon; ++m) {
         const int k = mon_ptr[m + 1] - mon_ptr[m];
-        if (k < 0 || k > 64)
-            return fail(HCN_EINVAL, "hcn_sys_load: monomial %d has %d pairs (0..64 allowed)", m, k);
+        if (k < 0 || k > n)
+            return fail(HCN_EINVAL, "hcn_sys_load: monomial %d has %d pairs (0..n allowed)", m, k);
         max_k = std::max(max_k, k);
     }
     const int npairs = mon_ptr[nmon];
@@ -389,9 +405,7 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
 }
 
 int hcn_sys_free(hcn_sys sys) {
-    if (!sys) return HCN_OK;
-    (void)hipFree(sys->dmem);
-    delete sys;
+    sys_release(sys);
     return HCN_OK;
 }
 
@@ -458,7 +472,7 @@ NewtonWs carve_newton(C &c, const SysView &v, int B) {
 
 struct TrackWs {
     NewtonWs nw;
-    double *x, *x_acc, *x_prev, *t;
+    double *x, *x_acc, *x_prev, *x_old, *t;
     int32_t *count;
 };
 
@@ -470,6 +484,7 @@ TrackWs carve_track(C &c, const SysView &v, int B) {
     w.x = c.template take<double>((size_t)B * v.n * W);
     w.x_acc = c.template take<double>((size_t)B * v.n * W);
     w.x_prev = c.template take<double>((size_t)B * v.n * W);
+    w.x_old = c.template take<double>((size_t)B * (MAX_PREDICTOR_ORDER - 1) * v.n * W);
     w.t = c.template take<double>((size_t)B);
     w.count = c.template take<int32_t>(1);
     return w;
@@ -623,7 +638,7 @@ int hcn_eval_jac(hcn_sys sys, int B, const double *x, double *f, double *J, void
 }
 
 size_t hcn_mgs_ws_bytes(int B, int N, int n, int P) {
-    if (B < 0 || n < 1 || (P != 2 && P != 4)) return 0;
+    if (B < 0 || n < 1 || (P != 1 && P != 2 && P != 4)) return 0;
     Carver c(nullptr);
     c.take<double>((size_t)B * (n + 1) * n * 2 * P);
     c.take<double>((size_t)B * n * P);
@@ -633,7 +648,7 @@ size_t hcn_mgs_ws_bytes(int B, int N, int n, int P) {
 
 int hcn_mgs_solve(int B, int N, int n, int P, double *A, double *b, double *dx, double *R,
                   int32_t *status, void *ws, size_t ws_bytes, void *stream) {
-    if (P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_mgs_solve: P must be 2 or 4");
+    if (P != 1 && P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_mgs_solve: P must be 1, 2 or 4");
     if (n < 1 || N < n || N > 4096)
         return fail(HCN_EINVAL, "hcn_mgs_solve: need 1 <= n <= N <= 4096 (N=%d n=%d)", N, n);
     if (B < 0) return fail(HCN_EINVAL, "hcn_mgs_solve: negative batch");
@@ -746,6 +761,8 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B, const 
         return fail(HCN_EINVAL, "hcn_track_paths: bad max_steps or end_iters");
     if (!(prm->max_dt > 0.0) || !(prm->min_dt > 0.0) || prm->max_dt > 1.0)
         return fail(HCN_EINVAL, "hcn_track_paths: need 0 < min_dt and 0 < max_dt <= 1");
+    if (prm->predictor_order < 0 || prm->predictor_order > MAX_PREDICTOR_ORDER)
+        return fail(HCN_EINVAL, "hcn_track_paths: predictor_order out of 0..%d", MAX_PREDICTOR_ORDER);
     if (B == 0) return HCN_OK;
     if (!x0 || !x_out || !results) return fail(HCN_EINVAL, "hcn_track_paths: NULL x0, x_out or results");
     const SysView &v = sys->v;
@@ -776,6 +793,7 @@ int hcn_track_paths(hcn_sys sys, const double *gamma, int relax_k, int B, const 
     ta.x = w.x;
     ta.x_acc = w.x_acc;
     ta.x_prev = w.x_prev;
+    ta.x_old = w.x_old;
     ta.x_out = x_out;
     ta.t = w.t;
     ta.res = results;
@@ -865,6 +883,8 @@ int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B, const
     if (B < 0) return fail(HCN_EINVAL, "hcn_newton_mixed: negative batch");
     if (prm->max_iter < 0 || prm->max_iter > 1000)
         return fail(HCN_EINVAL, "hcn_newton_mixed: max_iter out of 0..1000");
+    if (sys->v.P == 1)
+        return fail(HCN_EINVAL, "hcn_newton_mixed: the system is in double precision already");
     if (B == 0) return HCN_OK;
     if (!x) return fail(HCN_EINVAL, "hcn_newton_mixed: NULL x");
     const SysView &v = sys->v;
@@ -942,13 +962,19 @@ int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B, const
 }
 
 int hcn_set_mgs_variant(int variant) {
-    if (variant < 0 || variant > 4) return fail(HCN_EINVAL, "hcn_set_mgs_variant: 0..4");
+    if (variant < 0 || variant > 4 || variant == 3)
+        return fail(HCN_EINVAL, "hcn_set_mgs_variant: 0, 1, 2 or 4 (3 is not available)");
     g_mgs_variant = variant;
     return HCN_OK;
 }
 
 int hcn_set_mon_uniform(int on) {
     set_mon_uniform(on != 0);
+    return HCN_OK;
+}
+
+int hcn_set_mon_tree(int on) {
+    set_mon_tree(on != 0);
     return HCN_OK;
 }
 
@@ -965,7 +991,7 @@ int hcn_set_mgs_panel(int T) {
 
 int hcn_elementwise(int op, int P, int count, const double *a, const double *b, double *out,
                     void *stream) {
-    if (P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_elementwise: P must be 2 or 4");
+    if (P != 1 && P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_elementwise: P must be 1, 2 or 4");
     static const int ops[] = {0, 1, 2, 3, 4, 5, 10, 11, 12, 13, 14, 15, 20, 21, 22};
     if (std::find(std::begin(ops), std::end(ops), op) == std::end(ops))
         return fail(HCN_EINVAL, "hcn_elementwise: unknown op %d", op);

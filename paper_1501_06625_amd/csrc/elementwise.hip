@@ -80,7 +80,9 @@ int launch_elementwise(int op, int P, int count, const double *a, const double *
                        hipStream_t stream) {
     if (count == 0) return 0;
     dim3 grid((count + 255) / 256);
-    if (P == 2)
+    if (P == 1)
+        hipLaunchKernelGGL(k_elementwise<double>, grid, dim3(256), 0, stream, op, count, a, b, out);
+    else if (P == 2)
         hipLaunchKernelGGL(k_elementwise<dd>, grid, dim3(256), 0, stream, op, count, a, b, out);
     else
         hipLaunchKernelGGL(k_elementwise<qd>, grid, dim3(256), 0, stream, op, count, a, b, out);

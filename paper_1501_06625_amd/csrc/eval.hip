@@ -29,7 +29,34 @@ __global__ __launch_bounds__(256) void k_mon(MonArgs a) {
             __syncthreads();
         }
         const PointView pv{xb, 2 * a.xP, a.xP, table ? pows : nullptr};
-        if (m < a.s.nmon) mon_one<R, KB, MODE, UNI>(a.s, m, pv, a.scratch + (size_t)b * a.sc_pstride);
+        if (m < a.s.nmon) {
+            double *out = a.scratch + (size_t)b * a.sc_pstride;
+            if constexpr (KB == 0)
+                mon_one_long<R, MODE, UNI>(a.s, m, pv, out);
+            else
+                mon_one<R, KB, MODE, UNI>(a.s, m, pv, out);
+        }
+        if (table) __syncthreads();
+    }
+}
+
+// tree mode: G lanes per monomial (mon_tree), 256 / G monomials per workgroup
+template <class R, int G, bool UNI>
+__global__ __launch_bounds__(256) void k_mon_tree(MonArgs a) {
+    extern __shared__ double pows[];
+    const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int m = gid / G < a.s.nmon ? (int)(gid / G) : -1;
+    const int j = (int)(threadIdx.x % G);
+    const bool table = UNI && a.s.max_e > 2;
+    for (int b = blockIdx.y; b < a.B; b += gridDim.y) {
+        if (a.st && !a.st[b].c_active) continue;
+        const double *xb = a.x + (size_t)b * a.x_pstride;
+        if (table) {
+            stage_pows<R>(a.s, xb, a.xP, pows);
+            __syncthreads();
+        }
+        const PointView pv{xb, 2 * a.xP, a.xP, table ? pows : nullptr};
+        mon_tree<R, G, UNI>(a.s, m, j, pv, a.scratch + (size_t)b * a.sc_pstride);
         if (table) __syncthreads();
     }
 }
@@ -61,30 +88,60 @@ __global__ __launch_bounds__(256) void k_sum(SumArgs a) {
     }
 }
 
+// the unrolled monomial forms cover up to 64 variables; 0: the loop form
 static int kbucket(int max_k) {
     if (max_k <= 4) return 4;
     if (max_k <= 8) return 8;
     if (max_k <= 16) return 16;
     if (max_k <= 32) return 32;
-    return 64;
+    if (max_k <= 64) return 64;
+    return 0;
 }
 
 static bool g_mon_uniform = true;
+static bool g_mon_tree = false;
 
 bool mon_uniform_enabled() { return g_mon_uniform; }
 void set_mon_uniform(bool on) { g_mon_uniform = on; }
+void set_mon_tree(bool on) { g_mon_tree = on; }
+
+template <class R, int G>
+static void mon_tree_g(const MonArgs &a, hipStream_t stream) {
+    const long lanes = (long)a.s.nmon * G;
+    const dim3 grid((unsigned)((lanes + 255) / 256), a.B < 65535 ? a.B : 65535);
+    if (mon_uniform(a.s, limbs<R>::P))
+        hipLaunchKernelGGL((k_mon_tree<R, G, true>), grid, dim3(256), mon_stage_bytes(a.s, limbs<R>::P),
+                           stream, a);
+    else
+        hipLaunchKernelGGL((k_mon_tree<R, G, false>), grid, dim3(256), 0, stream, a);
+}
+
+// the tree form for the values and gradients of monomials of at most 64
+// variables, when enabled; false when the reverse form should run
+template <class R>
+static bool launch_mon_tree(const MonArgs &a, hipStream_t stream) {
+    if (!g_mon_tree || a.values_only || a.s.max_k > 64) return false;
+    const int k = a.s.max_k;
+    if (k <= 4) mon_tree_g<R, 4>(a, stream);
+    else if (k <= 8) mon_tree_g<R, 8>(a, stream);
+    else if (k <= 16) mon_tree_g<R, 16>(a, stream);
+    else if (k <= 32) mon_tree_g<R, 32>(a, stream);
+    else mon_tree_g<R, 64>(a, stream);
+    return true;
+}
 
 template <class R, int KB, bool UNI>
 static void mon_kb_u(const MonArgs &a, dim3 grid, size_t lds, hipStream_t stream) {
     // forward products in registers where they fit (DD up to 16, FP64 up to
     // 32 variables); QD and longer products park them in their output slots
-    constexpr bool freg = (limbs<R>::P == 2 && KB <= 16) || (limbs<R>::P == 1 && KB <= 32);
-    if (a.values_only)
+    constexpr bool freg = KB > 0 && ((limbs<R>::P == 2 && KB <= 16) || (limbs<R>::P == 1 && KB <= 32));
+    if (a.values_only) {
         hipLaunchKernelGGL((k_mon<R, KB, MON_VALUES, UNI>), grid, dim3(256), lds, stream, a);
-    else if (freg)
+    } else if constexpr (freg) {
         hipLaunchKernelGGL((k_mon<R, KB, MON_FREG, UNI>), grid, dim3(256), lds, stream, a);
-    else
+    } else {
         hipLaunchKernelGGL((k_mon<R, KB, MON_FSLOT, UNI>), grid, dim3(256), lds, stream, a);
+    }
 }
 
 template <class R, int KB>
@@ -100,12 +157,14 @@ static int launch_mon_t(const MonArgs &a, hipStream_t stream) {
     if (a.s.nmon == 0 || a.B == 0) return 0;
     dim3 grid((a.s.nmon + 255) / 256, a.B < 65535 ? a.B : 65535);
     ProfScope prof("eval_monomials", stream);
+    if (launch_mon_tree<R>(a, stream)) return (int)hipGetLastError();
     switch (kbucket(a.s.max_k)) {
         case 4: mon_kb<R, 4>(a, grid, stream); break;
         case 8: mon_kb<R, 8>(a, grid, stream); break;
         case 16: mon_kb<R, 16>(a, grid, stream); break;
         case 32: mon_kb<R, 32>(a, grid, stream); break;
-        default: mon_kb<R, 64>(a, grid, stream); break;
+        case 64: mon_kb<R, 64>(a, grid, stream); break;
+        default: mon_kb<R, 0>(a, grid, stream); break;
     }
     return (int)hipGetLastError();
 }

@@ -197,6 +197,168 @@ HCN_DEV void mon_one(const SysView &s, int m, const PointView &pv, double *out) 
     cstore(out + (size_t)(slot + stride) * W, escale(Bk, s.ex[m]));
 }
 
+// mon_one for monomials of any size (more variables than the unrolled forms
+// cover): the same operations in the same order as mon_one with MON_FSLOT
+// (or MON_VALUES), with loops over the monomial's own k, so the bits are
+// those of mon_one; forward products parked in the output slots.
+template <class R, int MODE, bool UNI = false>
+HCN_DEV void mon_one_long(const SysView &s, int m, const PointView &pv, double *out) {
+    static_assert(MODE != MON_FREG, "the long form parks its forward products in the slots");
+    constexpr int W = 2 * limbs<R>::P;
+    const int k = s.mon_k[m];
+    const int slot = s.mon_slot[m];
+    const int stride = s.mon_stride[m];
+    const cx<R> c = cload_s<R>(s.coef + (size_t)m * 2 * s.P, s.P);
+    if (k == 0) {
+        cstore(out + (size_t)slot * W, c);
+        return;
+    }
+    auto escale = [&](const cx<R> &d, int a) -> cx<R> {
+        if constexpr (UNI) return cscale_d(d, (double)a);
+        return exp_scale(d, a);
+    };
+    cx<R> Flast = czero<R>(), ylast = czero<R>(), pc = czero<R>();
+    bool has_pc = false;
+    for (int p = 0; p < k; ++p) {
+        int v;
+        const cx<R> y = load_y<R>(s, pv, p, m, v);
+        const int e = s.ex[(size_t)p * s.nmon + m];
+        if constexpr (UNI) {
+            cx<R> pw = y;
+            if (e >= 3) pw = cload<R>(pv.pows + ((size_t)(e - 3) * s.n + v) * W);
+            if (e == 1) pw = cone<R>();
+            pc = (p == 0) ? pw : cmul(pc, pw);
+        } else if (e >= 2) {
+            const cx<R> pw = cpow_small(y, e - 1);
+            pc = has_pc ? cmul(pc, pw) : pw;
+            has_pc = true;
+        }
+        if (p <= k - 2) {
+            const cx<R> Fp = (p == 0) ? y : cmul(Flast, y);
+            if (MODE == MON_FSLOT) cstore(out + (size_t)(slot + (p + 2) * stride) * W, Fp);
+            Flast = Fp;
+        } else {
+            ylast = y;
+        }
+    }
+    const cx<R> cp = UNI ? cmul(c, pc) : (has_pc ? cmul(c, pc) : c);
+    if (k == 1) {
+        cstore(out + (size_t)slot * W, cmul(cp, ylast));
+        if (MODE != MON_VALUES) cstore(out + (size_t)(slot + stride) * W, escale(cp, s.ex[m]));
+        return;
+    }
+    cx<R> Bk = cmul(cp, ylast);
+    cstore(out + (size_t)slot * W, cmul(Flast, Bk));
+    if (MODE == MON_VALUES) return;
+    cstore(out + (size_t)(slot + k * stride) * W,
+           escale(cmul(cp, Flast), s.ex[(size_t)(k - 1) * s.nmon + m]));
+    for (int p = k - 2; p >= 1; --p) {
+        const cx<R> Fpm1 = cload<R>(out + (size_t)(slot + (p + 1) * stride) * W);
+        cstore(out + (size_t)(slot + (p + 1) * stride) * W,
+               escale(cmul(Fpm1, Bk), s.ex[(size_t)p * s.nmon + m]));
+        int v;
+        Bk = cmul(Bk, load_y<R>(s, pv, p, m, v));
+    }
+    cstore(out + (size_t)(slot + stride) * W, escale(Bk, s.ex[m]));
+}
+
+// Tree mode (Section 3.2: the product of a monomial and all its products
+// with one factor left out as a circuit of G cooperating lanes, log G
+// levels, instead of one lane's reverse sweep).  Lane j of a group of G
+// (a power of two >= k) holds y_j (one past k), forms y_j^(a_j - 1), and
+// the group forms by shuffles, log2 G levels each:
+//   the product of those powers (a butterfly whose products take the lower
+//     lane's value first, so every lane holds the same bits), times c: c';
+//   the exclusive prefix products L_j = y_0 ... y_{j-1} and suffix products
+//     R_j = y_{j+1} ... y_{k-1} (Hillis-Steele scans);
+// then dm/dx_j = a_j (c' (L_j R_j)) and the value c' (L_{G-1} y_{G-1}) (the
+// total product, formed by the last lane's inclusive scan and broadcast).
+// Outputs go to the same slots as mon_one's.  The products are the same
+// mathematically as the reverse mode's, rounded in another order.
+template <class R>
+HCN_DEV cx<R> shfl_cx(const cx<R> &v, int src, int width);
+template <>
+HCN_DEV cx<double> shfl_cx(const cx<double> &v, int src, int width) {
+    return cx<double>{__shfl(v.re, src, width), __shfl(v.im, src, width)};
+}
+template <>
+HCN_DEV cx<dd> shfl_cx(const cx<dd> &v, int src, int width) {
+    return cx<dd>{dd{__shfl(v.re.hi, src, width), __shfl(v.re.lo, src, width)},
+                  dd{__shfl(v.im.hi, src, width), __shfl(v.im.lo, src, width)}};
+}
+template <>
+HCN_DEV cx<qd> shfl_cx(const cx<qd> &v, int src, int width) {
+    return cx<qd>{qd{__shfl(v.re.c0, src, width), __shfl(v.re.c1, src, width),
+                     __shfl(v.re.c2, src, width), __shfl(v.re.c3, src, width)},
+                  qd{__shfl(v.im.c0, src, width), __shfl(v.im.c1, src, width),
+                     __shfl(v.im.c2, src, width), __shfl(v.im.c3, src, width)}};
+}
+
+// every lane of the group calls this (lanes beyond the last monomial with
+// m = -1, which only take part in the shuffles)
+template <class R, int G, bool UNI>
+HCN_DEV void mon_tree(const SysView &s, int m, int j, const PointView &pv, double *out) {
+    constexpr int W = 2 * limbs<R>::P;
+    const bool live = m >= 0;
+    const int k = live ? s.mon_k[m] : 0;
+    const bool mine = j < k;
+    int v = 0, e = 1;
+    cx<R> y = cone<R>();
+    if (mine) {
+        y = load_y<R>(s, pv, j, m, v);
+        e = s.ex[(size_t)j * s.nmon + m];
+    }
+    // y^(a - 1): 1, y, or powers (from the staged table in the uniform form)
+    cx<R> pw = cone<R>();
+    if (e == 2) {
+        pw = y;
+    } else if (e >= 3) {
+        if constexpr (UNI)
+            pw = cload<R>(pv.pows + ((size_t)(e - 3) * s.n + v) * W);
+        else
+            pw = cpow_small(y, e - 1);
+    }
+    // c' = c * prod of the powers (butterfly, lower lane's value first)
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        const cx<R> o = shfl_cx(pw, (int)(threadIdx.x & 63) ^ d, 64);
+        pw = (j & d) ? cmul(o, pw) : cmul(pw, o);
+    }
+    // inclusive prefix products (Hillis-Steele), then exclusive by one lane
+    cx<R> pre = y;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        const int src = (int)(threadIdx.x & 63) - d;
+        const cx<R> o = shfl_cx(pre, src < 0 ? 0 : src, 64);
+        if (j >= d) pre = cmul(o, pre);
+    }
+    const int lane = (int)(threadIdx.x & 63);
+    const cx<R> total = shfl_cx(pre, lane - j + G - 1, 64);
+    cx<R> L = shfl_cx(pre, lane > 0 ? lane - 1 : 0, 64);
+    if (j == 0) L = cone<R>();
+    // exclusive suffix products
+    cx<R> suf = y;
+#pragma unroll
+    for (int d = 1; d < G; d <<= 1) {
+        const int src = lane + d;
+        const cx<R> o = shfl_cx(suf, src > 63 ? 63 : src, 64);
+        if (j + d < G) suf = cmul(suf, o);
+    }
+    cx<R> Rr = shfl_cx(suf, lane < 63 ? lane + 1 : 63, 64);
+    if (j == G - 1) Rr = cone<R>();
+    if (!live) return;
+    const int slot = s.mon_slot[m];
+    const int stride = s.mon_stride[m];
+    const cx<R> c = cload_s<R>(s.coef + (size_t)m * 2 * s.P, s.P);
+    if (k == 0) {
+        if (j == 0) cstore(out + (size_t)slot * W, c);
+        return;
+    }
+    const cx<R> cp = cmul(c, pw);
+    if (j == 0) cstore(out + (size_t)slot * W, cmul(cp, total));
+    if (mine) cstore(out + (size_t)(slot + (j + 1) * stride) * W, cscale_d(cmul(cp, cmul(L, Rr)), (double)e));
+}
+
 // The sum of the slots list[0], list[step], ..., list[(len-1) step], added
 // in list order.  The slot loads of SUM_BATCH entries (8; 4 in QD, whose
 // slots take twice the registers) are issued before their additions, so

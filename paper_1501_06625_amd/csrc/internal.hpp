@@ -59,15 +59,18 @@ struct PathState {
     // corrector
     double last, res, dxn, tol_res, tol_dx;
     int32_t c_status, c_iter, c_active, c_maxit;
-    // tracker
+    // tracker: accepted t values newest first (t_acc, t_prev, t_old[0..2])
     double t_acc, t_prev, dt, t;
+    double t_old[3];
     int32_t phase, nsucc, steps, accepted, newton_iters, end_iters, end_status,
-        have_prev, status, refine_started, finalized;
+        known, status, refine_started, finalized;
     // work counters: residual evaluations and solves since the path started
     int32_t evals, solves;
 };
 
 enum { PHASE_TRACK = 0, PHASE_REFINE = 1, PHASE_DONE = 2 };
+// highest degree of the predictor's extrapolation (Section 3.1)
+constexpr int MAX_PREDICTOR_ORDER = 4;
 enum { C_RUNNING = 100 };
 
 // MGS_MIXED_SOLVE: solve only (no update), for problems whose corrector is
@@ -135,17 +138,19 @@ int launch_mon(int RP, const MonArgs &a, hipStream_t stream);
 int launch_sum(int RP, const SumArgs &a, hipStream_t stream);
 int sum_nparts(const SysView &s, int jac);
 void set_mon_uniform(bool on);
+void set_mon_tree(bool on);
 int launch_mgs(int RP, const MgsArgs &a, hipStream_t stream);
 // multi-workgroup MGS for large single problems: variant 2 right-looking
-// (one launch per column step), 3 column-resident (cooperative); ints_dev
-// holds 2B+1 ints of workspace
+// (one launch per column step), 4 tiled; ints_dev holds B ints of workspace
 int launch_mgs_big(int P, const MgsArgs &a, int variant, int *ints_dev, hipStream_t stream);
-size_t mgs_res_lds(int N, int n, int P);
 int mgs_tiled_rpl(int N, int P);
 int mgs_panel_width();
 void set_mgs_panel_width(int T);
-// the device tables of a loaded system (capi.hip)
+// the device tables of a loaded system (capi.hip); references held by
+// batches and queued requests, the tables freed with the last
 SysView sys_view(hcn_sys s);
+void sys_retain(hcn_sys s);
+void sys_release(hcn_sys s);
 
 // kernel-variant table (tune.hip)
 int tune_mgs_group(int P, int N);
@@ -169,6 +174,7 @@ struct TrackArgs {
     double *x;       // working point [B][n][2P]
     double *x_acc;   // last accepted
     double *x_prev;  // the one before
+    double *x_old;   // the three before that, [B][3][n][2P] (NULL for order <= 1)
     double *x_out;
     double *t;       // trial t per path [B]
     hcn_path_result *res;

@@ -4,23 +4,15 @@
 // hundreds; the right-looking algorithm gives the most thread parallelism,
 // and combining it with left-looking tiles cuts memory traffic).
 //
-// Both variants apply, to every column j, the projections k = 0, 1, ..., j-1
-// in that order, and every column operation uses the same workgroup-wide
-// reduction (lane t sums rows t, t+256, ... in order; a 64-lane butterfly
-// adding the lower lane first; the four wavefront sums added in order), so
-// the two variants give bitwise identical results.
+// Every variant applies, to every column j, the projections k = 0, 1, ...,
+// j-1 in that order.
 //
 // Right-looking: one launch per column step k; the workgroup of trailing
-// column j > k forms r_kj = q_k^H a_j and a_j -= r_kj q_k on global memory;
-// the workgroup of column k+1 then also normalises it (r_{k+1,k+1}, q_{k+1}).
-// The trailing matrix is read and written once per step.
-//
-// Column-resident: one cooperative launch; workgroup w keeps columns
-// w, w+G, w+2G, ... in LDS for the whole factorisation.  The owner of column
-// k normalises it, publishes q_k to global memory and raises a per-problem
-// counter (release, device scope); the others wait for the counter (acquire,
-// bounded spin) and apply the projection to their resident columns.  Each
-// column is read from and written to global memory once.
+// column j > k forms r_kj = q_k^H a_j and a_j -= r_kj q_k on global memory
+// (lane t sums rows t, t+256, ... in order; a 64-lane butterfly adding the
+// lower lane first; the four wavefront sums added in order); the workgroup
+// of column k+1 then also normalises it (r_{k+1,k+1}, q_{k+1}).  The
+// trailing matrix is read and written once per step.
 //
 // Tiled (panel width T; mgs_tiled.hpp): the columns are taken T at a time.
 // A panel launch factors columns k0..k0+T-1 in one workgroup of T
@@ -191,101 +183,6 @@ __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
 }
 
 // ---------------------------------------------------------------------------
-// column-resident (cooperative launch, one problem per launch)
-// ---------------------------------------------------------------------------
-struct ResArgs {
-    int b;           // problem
-    int G;           // workgroups
-    int *counter;    // columns published so far for this problem
-    int *sing;       // [B]
-    int *timeout;    // set when a wait exceeds its bound
-    long spin_limit;
-};
-
-template <class R>
-__global__ __launch_bounds__(BT) void k_mgs_res(MgsArgs a, ResArgs r) {
-    constexpr int W = 2 * limbs<R>::P;
-    extern __shared__ double cols[];  // [ncols][N][W]
-    __shared__ cx<R> s_part[BT / 64];
-    __shared__ R s_rpart[BT / 64];
-    __shared__ R s_inv;
-    __shared__ int s_bad, s_stop;
-    const int b = r.b, w = blockIdx.x, G = r.G, n = a.n, N = a.N;
-    if (!problem_live(a, b)) return;
-    const size_t cstride = (size_t)N * W;
-    // owned columns j = w + c G, c = 0..nc-1
-    int nc = 0;
-    for (int j = w; j <= n; j += G) ++nc;
-    for (int c = 0; c < nc; ++c) {
-        const double *src = col_ptr(a, b, w + c * G);
-        for (size_t q = threadIdx.x; q < cstride; q += BT) cols[c * cstride + q] = src[q];
-    }
-    if (threadIdx.x == 0) s_stop = 0;
-    __syncthreads();
-    for (int k = 0; k < n; ++k) {
-        const double *qk;
-        if (k % G == w) {
-            double *ak = cols + (size_t)(k / G) * cstride;
-            const bool ok = col_normalise<R>(a, b, k, ak, s_rpart, &s_inv, &s_bad);
-            // the copy below maps lanes to doubles, not to the rows each lane scaled
-            __syncthreads();
-            if (ok) {
-                double *dst = col_ptr(a, b, k);
-                for (size_t q = threadIdx.x; q < cstride; q += BT) dst[q] = ak[q];
-            }
-            __threadfence();
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                if (!ok) r.sing[b] = 1;
-                __threadfence();
-                // a singular column releases every waiter at once
-                __hip_atomic_store(r.counter, ok ? k + 1 : n + 1, __ATOMIC_RELEASE,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (!ok) break;
-            qk = ak;
-        } else {
-            if (threadIdx.x == 0) {
-                long spins = 0;
-                int stop = 0;
-                while (__hip_atomic_load(r.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < k + 1) {
-                    if (++spins > r.spin_limit) {
-                        *r.timeout = 1;
-                        stop = 1;
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(2);
-                }
-                if (!stop && __hip_atomic_load(r.counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) > n)
-                    stop = 1;
-                s_stop = stop;
-            }
-            __syncthreads();
-            __atomic_thread_fence(__ATOMIC_ACQUIRE);
-            if (s_stop) break;
-            qk = col_ptr(a, b, k);
-        }
-        // apply projection k to every resident column j > k, in order
-        for (int c = 0; c < nc; ++c) {
-            const int j = w + c * G;
-            if (j <= k) continue;
-            double *aj = cols + (size_t)c * cstride;
-            const cx<R> rv = col_dot<R>(qk, aj, N, s_part);
-            if (threadIdx.x == 0)
-                cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * n + k) * W, rv);
-            col_axpy<R>(qk, aj, rv, N);
-        }
-        __syncthreads();
-    }
-    // the right-hand side column, projected, goes back to global memory
-    if (n % G == w && !s_stop) {
-        double *dst = col_ptr(a, b, n);
-        const double *src = cols + (size_t)(n / G) * cstride;
-        for (size_t q = threadIdx.x; q < cstride; q += BT) dst[q] = src[q];
-    }
-}
-
-// ---------------------------------------------------------------------------
 // tiled: panel and trailing launches over the bodies in mgs_tiled.hpp
 // ---------------------------------------------------------------------------
 // Panel k0..k1-1 of problem blockIdx.x; blockDim.x = 64 (k1 - k0).  The
@@ -364,55 +261,21 @@ __global__ void k_zero_int(int *p, int count) {
     if (q < count) p[q] = 0;
 }
 
-static int g_num_cus = 0;
-
-static int num_cus() {
-    if (g_num_cus == 0) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&g_num_cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (g_num_cus <= 0) g_num_cus = 1;
-    }
-    return g_num_cus;
-}
-
-// LDS bytes of the column-resident variant, or 0 when it does not fit
-size_t mgs_res_lds(int N, int n, int P) {
-    const int G = std::min(n + 1, num_cus());
-    const int nc = (n + 1 + G - 1) / G;
-    const size_t bytes = (size_t)nc * N * 2 * P * sizeof(double);
-    return bytes <= 120 * 1024 ? bytes : 0;
-}
-
 template <class R>
 static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s) {
-    // ints: sing[B], counter[B], timeout[1]
-    int *sing = ints, *counter = ints + a.B, *timeout = ints + 2 * a.B;
-    hipLaunchKernelGGL(k_zero_int, dim3((2 * a.B + 1 + 255) / 256), dim3(256), 0, s, ints,
-                       2 * a.B + 1);
+    // ints: sing[B]
+    int *sing = ints;
+    hipLaunchKernelGGL(k_zero_int, dim3((a.B + 255) / 256), dim3(256), 0, s, ints, a.B);
     if (a.mode == MGS_NEWTON_FIG2)
         hipLaunchKernelGGL(k_fig2_pre, dim3((a.B + 255) / 256), dim3(256), 0, s, a);
     {
         ProfScope prof("mgs", s);
         if (variant == 4) {
             launch_tiled<R>(a, sing, s);
-        } else if (variant == 2) {
+        } else {
             hipLaunchKernelGGL(k_mgs_rl<R>, dim3(1, a.B), dim3(BT), 0, s, a, -1, sing);
             for (int k = 0; k < a.n; ++k)
                 hipLaunchKernelGGL(k_mgs_rl<R>, dim3(a.n - k, a.B), dim3(BT), 0, s, a, k, sing);
-        } else {
-            const int G = std::min(a.n + 1, num_cus());
-            const size_t lds = mgs_res_lds(a.N, a.n, limbs<R>::P);
-            (void)hipFuncSetAttribute((const void *)k_mgs_res<R>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-            for (int b = 0; b < a.B; ++b) {
-                ResArgs r{b, G, counter + b, sing, timeout, 1L << 24};
-                MgsArgs ac = a;
-                void *args[] = {&ac, &r};
-                hipError_t e = hipLaunchCooperativeKernel((const void *)k_mgs_res<R>, dim3(G), dim3(BT),
-                                                          args, (unsigned)lds, s);
-                if (e != hipSuccess) return (int)e;
-            }
         }
         hipLaunchKernelGGL(k_mgs_finish<R>, dim3(a.B), dim3(BT), 0, s, a, sing);
     }
@@ -421,7 +284,6 @@ static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s)
 
 int launch_mgs_big(int P, const MgsArgs &a, int variant, int *ints, hipStream_t s) {
     if (a.B == 0) return 0;
-    if (variant == 3 && mgs_res_lds(a.N, a.n, P) == 0) variant = 2;
     if (variant == 4 && mgs_tiled_rpl(a.N, P) == 0) variant = 2;
     if (P == 1) return launch_big_t<double>(a, variant, ints, s);
     return P == 2 ? launch_big_t<dd>(a, variant, ints, s) : launch_big_t<qd>(a, variant, ints, s);

@@ -50,6 +50,8 @@ int size_class(int n) {
     return c;
 }
 
+// A request holds a reference on its system from submission until it is
+// fetched or the server is destroyed.
 struct Request {
     int64_t id = 0, seq = 0;
     hcn_sys sys = nullptr;
@@ -59,6 +61,7 @@ struct Request {
     double t_arrival = 0, t_admit = 0, t_done = 0;
     hcn_path_result res = {};
     std::vector<double> x_out;
+    ~Request() { hcn::sys_release(sys); }
 };
 
 struct Lane {
@@ -123,14 +126,15 @@ int admit_one(hcn_server_s *s, Lane &ln, bool *admitted) {
     int q = 0;
     while (q < ln.cap && ln.slots[q]) ++q;
     if (q == ln.cap) return HCN_OK;
+    // the request leaves the queue only once its slot is set up
     Request *r = ln.queue.front();
-    ln.queue.pop_front();
     double *x0d = ln.stage + (size_t)q * ln.max_n * 2 * ln.P;
     if (hipMemcpyAsync(x0d, r->x0.data(), sizeof(double) * r->x0.size(), hipMemcpyHostToDevice,
                        ln.stream) != hipSuccess)
         return sfail(HCN_EDEVICE, "hcn_server_pump: start point upload failed");
     const int rc = hcn_batch_add(ln.batch, q, r->sys, r->gamma, x0d, ln.stream);
     if (rc) return sfail(rc, hcn_batch_last_error());
+    ln.queue.pop_front();
     r->t_admit = s->now();
     ln.slots[q] = r;
     ++ln.running;
@@ -237,7 +241,8 @@ int hcn_server_submit(hcn_server s, int64_t id, hcn_sys sys, const double *gamma
                       const double *x0, double t_arrival) {
     if (!s || !sys || !gamma || !x0) return sfail(HCN_EINVAL, "hcn_server_submit: NULL argument");
     hcn_sys_info_t info;
-    hcn_sys_info(sys, &info);
+    if (hcn_sys_info(sys, &info) != HCN_OK) return sfail(HCN_EINVAL, "hcn_server_submit: bad system");
+    if (info.P != 2 && info.P != 4) return sfail(HCN_EINVAL, "hcn_server_submit: DD or QD systems only");
     const int l = info.P == 2 ? 0 : 1;
     if (info.N != info.n || info.n > s->max_n) {
         ++s->rejected;
@@ -251,6 +256,7 @@ int hcn_server_submit(hcn_server s, int64_t id, hcn_sys sys, const double *gamma
     auto *r = new Request;
     r->id = id;
     r->seq = s->seq++;
+    hcn::sys_retain(sys);
     r->sys = sys;
     r->P = info.P;
     r->n = info.n;

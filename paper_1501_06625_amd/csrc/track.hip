@@ -67,6 +67,8 @@ HCN_DEV TrackPath path_of(const TrackArgs &a, int b) {
     p.x = a.x + off;
     p.x_acc = a.x_acc + off;
     p.x_prev = a.x_prev + off;
+    p.old_stride = (long)a.n * 2 * a.P;
+    p.x_old = a.x_old ? a.x_old + (size_t)(MAX_PREDICTOR_ORDER - 1) * off : nullptr;
     p.x_out = a.x_out + off;
     p.t = a.t + b;
     p.res = a.res + b;
@@ -104,7 +106,9 @@ __global__ void k_track_count(TrackArgs a) {
 
 int launch_track_init(const TrackArgs &a, const double *x0, hipStream_t s) {
     if (a.B == 0) return 0;
-    if (a.P == 2)
+    if (a.P == 1)
+        hipLaunchKernelGGL(k_track_init<double>, dim3(a.B), dim3(TRK_THREADS), 0, s, a, x0);
+    else if (a.P == 2)
         hipLaunchKernelGGL(k_track_init<dd>, dim3(a.B), dim3(TRK_THREADS), 0, s, a, x0);
     else
         hipLaunchKernelGGL(k_track_init<qd>, dim3(a.B), dim3(TRK_THREADS), 0, s, a, x0);
@@ -113,7 +117,9 @@ int launch_track_init(const TrackArgs &a, const double *x0, hipStream_t s) {
 
 int launch_track_begin(const TrackArgs &a, hipStream_t s) {
     if (a.B == 0) return 0;
-    if (a.P == 2)
+    if (a.P == 1)
+        hipLaunchKernelGGL(k_track_begin<double>, dim3(a.B), dim3(TRK_THREADS), 0, s, a);
+    else if (a.P == 2)
         hipLaunchKernelGGL(k_track_begin<dd>, dim3(a.B), dim3(TRK_THREADS), 0, s, a);
     else
         hipLaunchKernelGGL(k_track_begin<qd>, dim3(a.B), dim3(TRK_THREADS), 0, s, a);
@@ -122,7 +128,9 @@ int launch_track_begin(const TrackArgs &a, hipStream_t s) {
 
 int launch_track_end(const TrackArgs &a, hipStream_t s) {
     if (a.B == 0) return 0;
-    if (a.P == 2)
+    if (a.P == 1)
+        hipLaunchKernelGGL(k_track_end<double>, dim3(a.B), dim3(TRK_THREADS), 0, s, a);
+    else if (a.P == 2)
         hipLaunchKernelGGL(k_track_end<dd>, dim3(a.B), dim3(TRK_THREADS), 0, s, a);
     else
         hipLaunchKernelGGL(k_track_end<qd>, dim3(a.B), dim3(TRK_THREADS), 0, s, a);

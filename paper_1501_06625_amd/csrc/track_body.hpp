@@ -2,9 +2,10 @@
 // run by one workgroup per path; shared by the single-system tracker
 // (track.hip) and the slot-table batch (batch.hip).
 //
-// begin: trial t = min(1, t_acc + dt) and the predicted point (linear
-// extrapolation through the two last accepted points, constant before the
-// second; Section 3.1); arms the corrector.  end: on success accept, count
+// begin: trial t = min(1, t_acc + dt) and the predicted point (Section 3.1:
+// the polynomial through the last accepted points, of degree
+// predictor_order or one less than the points known, evaluated in Lagrange
+// form); arms the corrector.  end: on success accept, count
 // it and once more than two successes are counted double dt up to max_dt;
 // on failure reset the count and halve dt, failing below min_dt; more than
 // max_steps steps fail the path.  After t = 1 the corrector refines with
@@ -20,9 +21,16 @@ struct TrackPath {
     int n;
     PathState *st;
     double *x, *x_acc, *x_prev, *x_out;
+    double *x_old;      // the 3rd..5th newest accepted points (NULL: order <= 1)
+    long old_stride;    // doubles between two of them
     double *t;
     hcn_path_result *res;
 };
+
+// accepted point j (0 the newest) of a path
+HCN_DEV const double *hist_point(const TrackPath &p, int j) {
+    return j == 0 ? p.x_acc : j == 1 ? p.x_prev : p.x_old + (size_t)(j - 2) * p.old_stride;
+}
 
 template <class R>
 HCN_DEV void track_init_one(const TrackArgs &a, const TrackPath &p, const double *x0) {
@@ -34,6 +42,7 @@ HCN_DEV void track_init_one(const TrackArgs &a, const TrackPath &p, const double
     if (threadIdx.x == 0) {
         PathState s = {};
         s.t_acc = 0.0;
+        s.known = 1;
         s.dt = a.max_dt;
         s.phase = PHASE_TRACK;
         s.status = HCN_OK;
@@ -46,7 +55,8 @@ template <class R>
 HCN_DEV void track_begin_one(const TrackArgs &a, const TrackPath &p) {
     constexpr int W = 2 * limbs<R>::P;
     __shared__ int s_mode;  // 0 idle, 1 predict, 2 copy x_acc (refine start)
-    __shared__ double s_t;
+    __shared__ int s_deg;
+    __shared__ double s_t, s_ts[MAX_PREDICTOR_ORDER + 1];
     PathState &st = *p.st;
     if (threadIdx.x == 0) {
         int mode = 0;
@@ -70,6 +80,13 @@ HCN_DEV void track_begin_one(const TrackArgs &a, const TrackPath &p) {
                 st.c_active = a.max_iter > 0 ? 1 : 0;
                 st.c_status = a.max_iter > 0 ? C_RUNNING : HCN_NOT_CONVERGED;
                 s_t = t;
+                int deg = st.known - 1;
+                if (deg > a.predictor_order) deg = a.predictor_order;
+                if (deg < 0) deg = 0;
+                s_deg = deg;
+                s_ts[0] = st.t_acc;
+                s_ts[1] = st.t_prev;
+                for (int j = 2; j <= MAX_PREDICTOR_ORDER; ++j) s_ts[j] = st.t_old[j - 2];
                 mode = 1;
             }
         } else if (st.phase == PHASE_REFINE && !st.refine_started) {
@@ -92,20 +109,33 @@ HCN_DEV void track_begin_one(const TrackArgs &a, const TrackPath &p) {
     __syncthreads();
     const int mode = s_mode;
     if (mode == 0) return;
-    if (mode == 2 || !st.have_prev || a.predictor_order < 1) {
+    const int deg = mode == 2 ? 0 : s_deg;
+    if (deg == 0) {
         for (int q = threadIdx.x; q < p.n * W; q += blockDim.x) p.x[q] = p.x_acc[q];
         return;
     }
-    // secant: x = x1 + r (x1 - x0), r = (t - t1) / (t1 - t0)
+    // Lagrange weights w_j = prod_{m != j} (t - t_m) / prod_{m != j} (t_j - t_m),
+    // products in m order from the double differences, formed alike in every
+    // lane; then x = sum_j w_j x_j over j ascending
     const double t = s_t;
-    const R num = rmake<R>(t - st.t_acc);
-    const R den = rmake<R>(st.t_acc - st.t_prev);
-    const R ratio = div(num, den);
+    R w[MAX_PREDICTOR_ORDER + 1];
+    for (int j = 0; j <= deg; ++j) {
+        R num = rmake<R>(1.0), den = rmake<R>(1.0);
+        bool first = true;
+        for (int m = 0; m <= deg; ++m) {
+            if (m == j) continue;
+            const R a_m = rmake<R>(t - s_ts[m]);
+            const R b_m = rmake<R>(s_ts[j] - s_ts[m]);
+            num = first ? a_m : mul(num, a_m);
+            den = first ? b_m : mul(den, b_m);
+            first = false;
+        }
+        w[j] = div(num, den);
+    }
     for (int i = threadIdx.x; i < p.n; i += blockDim.x) {
-        const cx<R> x1 = cload<R>(p.x_acc + (size_t)i * W);
-        const cx<R> xp = cload<R>(p.x_prev + (size_t)i * W);
-        const cx<R> d = csub(x1, xp);
-        cstore(p.x + (size_t)i * W, cadd(x1, cscale(ratio, d)));
+        cx<R> acc = cscale(w[0], cload<R>(p.x_acc + (size_t)i * W));
+        for (int j = 1; j <= deg; ++j) acc = cadd(acc, cscale(w[j], cload<R>(hist_point(p, j) + (size_t)i * W)));
+        cstore(p.x + (size_t)i * W, acc);
     }
 }
 
@@ -126,7 +156,8 @@ HCN_DEV void track_write_result(const TrackPath &p, const PathState &st) {
 template <class R>
 HCN_DEV void track_end_one(const TrackArgs &a, const TrackPath &p) {
     constexpr int W = 2 * limbs<R>::P;
-    __shared__ int s_copy;  // 0 none, 1 accept (x_prev <- x_acc, x_acc <- x),
+    __shared__ int s_copy;  // 0 none, 1 accept (the accepted points move one
+                            // back, x_acc <- x),
                             // 2 out <- x, 3 out <- x_acc, 4 accept and out <- x
     PathState &st = *p.st;
     if (threadIdx.x == 0) {
@@ -135,9 +166,12 @@ HCN_DEV void track_end_one(const TrackArgs &a, const TrackPath &p) {
             const int cs = st.c_status;
             st.newton_iters += st.c_iter;
             if (cs == HCN_OK) {
+                st.t_old[2] = st.t_old[1];
+                st.t_old[1] = st.t_old[0];
+                st.t_old[0] = st.t_prev;
                 st.t_prev = st.t_acc;
-                st.have_prev = 1;
                 st.t_acc = st.t;
+                if (st.known <= MAX_PREDICTOR_ORDER) st.known += 1;
                 st.accepted += 1;
                 st.nsucc += 1;
                 if (st.nsucc > 2) {
@@ -190,6 +224,12 @@ HCN_DEV void track_end_one(const TrackArgs &a, const TrackPath &p) {
     if (copy == 0) return;
     for (int q = threadIdx.x; q < p.n * W; q += blockDim.x) {
         if (copy == 1 || copy == 4) {
+            if (p.x_old) {
+                double *o = p.x_old + q;
+                o[2 * p.old_stride] = o[p.old_stride];
+                o[p.old_stride] = o[0];
+                o[0] = p.x_prev[q];
+            }
             const double xa = p.x_acc[q];
             p.x_prev[q] = xa;
             p.x_acc[q] = p.x[q];

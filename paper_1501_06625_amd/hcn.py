@@ -63,7 +63,7 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_sys_degrees", "hcn_eval_ws_bytes", "hcn_eval_jac", "hcn_mgs_ws_bytes",
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
-           "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_set_chunk_bytes", "hcn_set_mon_uniform", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
+           "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_set_chunk_bytes", "hcn_set_mon_uniform", "hcn_set_mon_tree", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
            "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load", "hcn_autotune",
            "hcn_batch_create", "hcn_batch_destroy", "hcn_batch_device_bytes",
            "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_set_split", "hcn_batch_set_persistent", "hcn_batch_step",
@@ -105,6 +105,7 @@ def _load():
     lib.hcn_set_mgs_panel.argtypes = [ci]
     lib.hcn_set_chunk_bytes.argtypes = [sz]
     lib.hcn_set_mon_uniform.argtypes = [ci]
+    lib.hcn_set_mon_tree.argtypes = [ci]
     lib.hcn_newton_mixed_ws_bytes.argtypes = [vp, ci]
     lib.hcn_newton_mixed_ws_bytes.restype = sz
     lib.hcn_newton_mixed.argtypes = lib.hcn_newton.argtypes
@@ -327,6 +328,9 @@ def newton(sys: System, x: torch.Tensor, gamma=None, t: Optional[torch.Tensor] =
     return status, iters, norms
 
 
+# refinement tolerance at t = 1 per precision (double, double-double, quad-double)
+END_TOL = {1: 1e-14, 2: 1e-28, 4: 1e-58}
+
 DEFAULT_TRACK = dict(max_iter=3, tol_res=1e-12, tol_dx=1e-12, max_eq_val=1.0,
                      max_dt=2.0 ** -4, min_dt=2.0 ** -40, max_steps=1500,
                      end_iters=10, end_tol=None, predictor_order=1)
@@ -338,7 +342,7 @@ def track_paths(sys: System, gamma, x0: torch.Tensor, relax_k: int = 1, **kw):
     p = dict(DEFAULT_TRACK)
     p.update(kw)
     if p["end_tol"] is None:
-        p["end_tol"] = 1e-28 if sys.P == 2 else 1e-58
+        p["end_tol"] = END_TOL[sys.P]
     x0b, batched = _batched(x0.contiguous(), 3)
     B = x0b.shape[0]
     xo = torch.empty_like(x0b)
@@ -392,7 +396,7 @@ def profile_query(kernel: str):
     return ms.value, cnt.value
 
 
-MGS_AUTO, MGS_WORKGROUP, MGS_RIGHT_LOOKING, MGS_COLUMN_RESIDENT, MGS_TILED = 0, 1, 2, 3, 4
+MGS_AUTO, MGS_WORKGROUP, MGS_RIGHT_LOOKING, MGS_TILED = 0, 1, 2, 4
 
 
 def set_mgs_variant(variant: int) -> None:
@@ -408,6 +412,11 @@ def set_mgs_panel(T: int) -> None:
 def set_mon_uniform(on: bool) -> None:
     """Uniform (1) or branching (0) common factor in the monomial kernels (see hcn_set_mon_uniform)."""
     _check(_lib.hcn_set_mon_uniform(1 if on else 0))
+
+
+def set_mon_tree(on: bool) -> None:
+    """Tree mode (1) or reverse mode (0) for the monomials (see hcn_set_mon_tree)."""
+    _check(_lib.hcn_set_mon_tree(1 if on else 0))
 
 
 def set_chunk_bytes(nbytes: int) -> None:
@@ -454,7 +463,7 @@ def track_params(P: int, **kw) -> _TrackParams:
     p = dict(DEFAULT_TRACK)
     p.update(kw)
     if p["end_tol"] is None:
-        p["end_tol"] = 1e-28 if P == 2 else 1e-58
+        p["end_tol"] = END_TOL[P]
     return _TrackParams(int(p["max_iter"]), float(p["tol_res"]), float(p["tol_dx"]),
                         float(p["max_eq_val"]), float(p["max_dt"]), float(p["min_dt"]),
                         int(p["max_steps"]), int(p["end_iters"]), float(p["end_tol"]),

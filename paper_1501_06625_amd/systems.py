@@ -367,3 +367,141 @@ def system_from_monomials(N: int, n: int, P: int, eqs, coefs: np.ndarray,
                       exp=np.asarray(exp, dtype=np.int32),
                       coef=np.asarray(coefs, dtype=np.float64).reshape(-1, 2, P),
                       name=name)
+
+
+# ---------------------------------------------------------------------------
+# the paper's two benchmark families, as structure (Section 4)
+# ---------------------------------------------------------------------------
+
+def cyclic_system(n: int, P: int = DD) -> PolySystem:
+    """The cyclic n-roots system (Section 4.2): f_1 = x_0 + ... + x_{n-1};
+    f_i = sum_{j=0}^{n-1} prod_{k=j}^{j+i-1} x_{k mod n} for i = 2..n-1;
+    f_n = x_0 x_1 ... x_{n-1} - 1.  Equation i has n monomials of i
+    variables (its degree is i), so the system has monomials of every size
+    1..n; coefficients are 1 (and -1 for the constant)."""
+    eqs, coefs = [], []
+    one = np.zeros((2, P))
+    one[0, 0] = 1.0
+    for i in range(1, n):
+        mons = []
+        for j in range(n):
+            mons.append([((j + q) % n, 1) for q in range(i)])
+            coefs.append(one)
+        eqs.append(mons)
+    eqs.append([[(q, 1) for q in range(n)], []])
+    coefs.append(one)
+    coefs.append(-one)
+    return system_from_monomials(n, n, P, eqs, np.asarray(coefs), name=f"cyclic{n}")
+
+
+def cyclic_root(n: int, P: int = DD) -> np.ndarray:
+    """A root of the cyclic n-roots system found by substitution:
+    x_j = w^j for odd n and x_j = e^{i pi / n} w^j for even n, w = e^{2 pi i / n}
+    (then every f_i, i < n, is a multiple of sum_j w^{ij} = 0 and the product
+    of all x_j is 1); rounded to P limbs at 320 bits: [n][2][P]."""
+    out = np.zeros((n, 2, P))
+    with mpmath.workprec(_MP_PREC):
+        for j in range(n):
+            ang = 2 * mpmath.pi * mpmath.mpf(j) / n
+            if n % 2 == 0:
+                ang += mpmath.pi / n
+            c, s_ = mpmath.cos_sin(ang)
+            out[j, 0] = mp_to_limbs(c, P)
+            out[j, 1] = mp_to_limbs(s_, P)
+    return out
+
+
+def pieri_variables(m: int, p: int):
+    """Positions (row, column) of the unknowns of the (m+p) x p localization
+    pattern (Section 4.1): column c has its 1 at row c and unknowns at rows
+    c+1 .. c+m; they are introduced one at a time, the last column first,
+    top to bottom within a column."""
+    order = []
+    for c in range(p - 1, -1, -1):
+        for r in range(c + 1, c + m + 1):
+            order.append((r, c))
+    return order
+
+
+def determinantal_system(m: int, p: int, k: int, seed: int = 0, P: int = DD) -> PolySystem:
+    """A system of minor expansions (Section 4.1, equation (5)): the unknowns
+    are the first k entries of the Pieri pattern of an (m+p) x p matrix X
+    (pieri_variables; later pattern entries are 0), and equation i is
+    det(K_i^T X) = 0 for a random complex (m+p) x p matrix K_i, i = 1..k,
+    which is det(A_i | X) = 0 for an A_i whose columns span the orthogonal
+    complement of K_i's.  By Cauchy-Binet,
+        det(K^T X) = sum over p-row subsets S of det(K[S]) det(X[S]),
+    and det(X[S]) expands by Leibniz into products of entries from distinct
+    rows and columns: every monomial is a product of at most p distinct
+    unknowns.  The coefficients (sums of signed p x p minors of K_i, in
+    double precision: the K_i are random draws) are exact doubles in limb
+    0.  Seeded with 1000*5 + seed."""
+    from itertools import combinations, permutations
+    n = m + p
+    order = pieri_variables(m, p)
+    if not 1 <= k <= len(order):
+        raise ValueError("k out of range")
+    var_at = {pos: q for q, pos in enumerate(order[:k])}
+    # terms (S, sign, monomial) of det(X[S]) with every entry nonzero
+    subsets = list(combinations(range(n), p))
+    perms = list(permutations(range(p)))
+
+    def sign(pm):
+        s_, seen = 1, list(pm)
+        for a in range(len(seen)):
+            for b in range(a + 1, len(seen)):
+                if seen[a] > seen[b]:
+                    s_ = -s_
+        return s_
+
+    mono_index = {}
+    t_sub, t_sign, t_mono = [], [], []
+    for si, S in enumerate(subsets):
+        for pm in perms:
+            vs = []
+            ok = True
+            for c in range(p):
+                r = S[pm[c]]
+                if r == c:
+                    continue  # the pivot 1
+                if (r, c) in var_at:
+                    vs.append(var_at[(r, c)])
+                else:
+                    ok = False
+                    break
+            if not ok:
+                continue
+            key = tuple(sorted(vs))
+            if key not in mono_index:
+                mono_index[key] = len(mono_index)
+            t_sub.append(si)
+            t_sign.append(sign(pm))
+            t_mono.append(mono_index[key])
+    monos = sorted(mono_index, key=lambda key: (len(key), key))
+    rank = {key: q for q, key in enumerate(monos)}
+    remap = np.array([rank[key] for key in mono_index], dtype=np.int64)
+    t_mono = remap[np.array(t_mono, dtype=np.int64)]
+    rng = rng_for(5, seed)
+    K = rng.standard_normal((k, n, p)) + 1j * rng.standard_normal((k, n, p))
+    idx = np.array(subsets, dtype=np.int64)              # [nsub][p]
+    minors = np.linalg.det(K[:, idx, :])                 # [k][nsub]
+    coef = np.zeros((k, len(monos)), dtype=np.complex128)
+    contrib = minors[:, np.array(t_sub)] * np.array(t_sign)[None, :]
+    for i in range(k):
+        np.add.at(coef[i], t_mono, contrib[i])
+    # every equation has the same support (the coefficients are nonzero with
+    # probability one): the tables of one equation repeated k times
+    M = len(monos)
+    lens = np.array([len(key) for key in monos], dtype=np.int64)
+    flat = np.array([v for key in monos for v in key], dtype=np.int32)
+    mon_ptr = np.zeros(k * M + 1, dtype=np.int64)
+    mon_ptr[1:] = np.cumsum(np.tile(lens, k))
+    coefs = np.zeros((k * M, 2, P))
+    coefs[:, 0, 0] = coef.real.ravel()
+    coefs[:, 1, 0] = coef.imag.ravel()
+    return PolySystem(N=k, n=k, P=P,
+                      eq_ptr=np.arange(0, k * M + 1, M, dtype=np.int32),
+                      mon_ptr=mon_ptr.astype(np.int32),
+                      var=np.tile(flat, k).astype(np.int32),
+                      exp=np.ones(k * flat.size, dtype=np.int32),
+                      coef=coefs, name=f"det-m{m}-p{p}-k{k}")

@@ -40,24 +40,39 @@ def test_host_side_argument_errors():
     z = np.zeros(4, dtype=np.int32)
     p = z.ctypes.data_as(ctypes.c_void_p)
     assert lib.hcn_sys_load(ctypes.byref(h), 2, 2, 3, p, p, p, p, p) == hcn.EINVAL
-    assert b"P must be 2 or 4" in lib.hcn_last_error()
+    assert b"P must be 1, 2 or 4" in lib.hcn_last_error()
     assert lib.hcn_sys_load(ctypes.byref(h), 1, 2, 2, p, p, p, p, p) == hcn.EINVAL
     assert lib.hcn_mgs_solve(1, 2, 3, 2, None, None, None, None, None, None, 0, None) == hcn.EINVAL
     assert lib.hcn_elementwise(99, 2, 1, None, None, None, None) == hcn.EINVAL
     assert lib.hcn_version() == 100
     assert lib.hcn_set_mgs_variant(5) == hcn.EINVAL
+    # the column-resident variant is not available
+    assert lib.hcn_set_mgs_variant(3) == hcn.EINVAL
+    assert lib.hcn_set_mgs_variant(0) == hcn.OK
+    # extrapolation beyond degree 4 is refused before any allocation
+    bad = hcn.track_params(2, predictor_order=5)
+    assert lib.hcn_batch_create(ctypes.byref(h), 2, 4, 8, 64, 4, ctypes.byref(bad), 1, 0) == hcn.EINVAL
+    neg = hcn.track_params(2, predictor_order=-1)
+    assert lib.hcn_batch_create(ctypes.byref(h), 2, 4, 8, 64, 4, ctypes.byref(neg), 1, 0) == hcn.EINVAL
+    # complex double batches are not offered (DD and QD only)
+    ok = hcn.track_params(2)
+    assert lib.hcn_batch_create(ctypes.byref(h), 1, 4, 8, 64, 4, ctypes.byref(ok), 1, 0) == hcn.EINVAL
     assert lib.hcn_set_mgs_panel(0) == hcn.EINVAL
     assert lib.hcn_set_mgs_panel(17) == hcn.EINVAL
     assert lib.hcn_tune_set(2, 32, 16, 5) == hcn.EINVAL
     assert lib.hcn_batch_set_persistent(None, 1) == hcn.EINVAL
     assert lib.hcn_tune_set(2, 32, 12, 0) == hcn.EINVAL
     # a repeated variable inside a monomial is rejected
-    eq_ptr = np.array([0, 1], dtype=np.int32)
+    eq_ptr = np.array([0, 1, 1], dtype=np.int32)
     mon_ptr = np.array([0, 2], dtype=np.int32)
     var = np.array([0, 0], dtype=np.int32)
     ex = np.array([1, 1], dtype=np.int32)
     coef = np.zeros(4)
     q = lambda a: a.ctypes.data_as(ctypes.c_void_p)
-    assert lib.hcn_sys_load(ctypes.byref(h), 1, 1, 2, q(eq_ptr), q(mon_ptr), q(var), q(ex),
+    assert lib.hcn_sys_load(ctypes.byref(h), 2, 2, 2, q(eq_ptr), q(mon_ptr), q(var), q(ex),
                             q(coef)) == hcn.EINVAL
     assert b"repeated" in lib.hcn_last_error()
+    # a monomial cannot have more factors than there are unknowns
+    assert lib.hcn_sys_load(ctypes.byref(h), 1, 1, 2, q(eq_ptr), q(mon_ptr), q(var), q(ex),
+                            q(coef)) == hcn.EINVAL
+    assert b"pairs" in lib.hcn_last_error()

@@ -1,0 +1,432 @@
+"""GPU parity for inputs beyond the basic workloads, all through the C ABI:
+exponents up to 15, the relaxation exponent k >= 2 of equation (1),
+extrapolation of degree 2..4 (Section 3.1), QD tracking of random systems,
+overdetermined Newton (N > n, least squares through the same MGS), a
+system of the shape of the 64-system batch (n = 96, 64 monomials of 12
+variables) through the slot-table batch in plain and mixed precision, and
+systems freed by their owner while a batch or a server still uses them."""
+import numpy as np
+import pytest
+
+from oracle import mpref as M
+from oracle import oracle as O
+from paper_1501_06625_amd import systems as S
+from tests.gpu_util import GATE, UNIT, lead_complex, limb_diff, term_scales
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1501_06625_amd import hcn
+    return hcn
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _bitwise_equal(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return a.shape == b.shape and np.array_equal(a.view(np.int64) | 0, b.view(np.int64) | 0) \
+        or np.array_equal(a, b)
+
+
+def _check_eval(H, ps, xs):
+    sysd = H.System(ps)
+    f, J = H.eval_jac(sysd, dev(xs))
+    f, J = host(f), host(J)
+    for q in range(xs.shape[0]):
+        fo, Jo = O.eval_jac(ps, xs[q])
+        Sf, SJ = term_scales(ps, xs[q])
+        ef = np.abs(limb_diff(f[q], fo)) / np.maximum(Sf, 1e-300)
+        eJ = np.abs(limb_diff(J[q], Jo)) / np.maximum(SJ, 1e-300)
+        assert ef.max() <= GATE[ps.P] and eJ.max() <= GATE[ps.P], (q, ef.max(), eJ.max())
+
+
+# ---------------------------------------------------------------------------
+# exponents above three
+# ---------------------------------------------------------------------------
+
+def _points_near_unit(rng, B, n, P):
+    """B points with coordinates r exp(i phi), r ~ U[0.9, 1.1] (so that powers
+    up to 15 neither vanish nor explode), rounded to P limbs at 320 bits."""
+    import mpmath
+    out = np.zeros((B, n, 2, P))
+    with mpmath.workprec(320):
+        for b in range(B):
+            for i in range(n):
+                r, ph = rng.uniform(0.9, 1.1), rng.uniform(0, 2 * np.pi)
+                out[b, i] = S.complex_to_limbs(mpmath.mpf(r) * mpmath.expj(mpmath.mpf(ph)), P)
+    return out
+
+
+@pytest.mark.parametrize("P", [2, 4])
+@pytest.mark.parametrize("n,uniform", [(12, True), (12, False), (90, True)])
+def test_eval_high_exponents(H, P, n, uniform):
+    """Exponents 1..15 (the largest sys_load accepts): the power table of
+    the uniform form (n = 12 fits its LDS budget; n = 90 does not and falls
+    back to branching) and the branching form, against the oracle's plain
+    definition."""
+    rng = S.rng_for(7, 10 * P + n + uniform)
+    ps = S.random_system(rng, n, n, (3, 8), (1, 5), tuple(range(1, 16)), P, const_term=True)
+    assert ps.exp.max() == 15 and ps.exp.min() == 1
+    xs = _points_near_unit(rng, 3, n, P)
+    H.set_mon_uniform(uniform)
+    try:
+        _check_eval(H, ps, xs)
+    finally:
+        H.set_mon_uniform(True)
+
+
+# ---------------------------------------------------------------------------
+# relaxation exponent k >= 2 (equation (1): gamma (1 - t)^k g + t^k f)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("P", [2, 4])
+@pytest.mark.parametrize("k", [2, 3])
+def test_newton_step_relaxation(H, P, k):
+    ps = S.small_track_system(2, P)
+    g = O.total_degree_start(ps)
+    rng = S.rng_for(7, 40 + P + k)
+    gam = S.random_unit_gamma(rng, P)
+    xs = S.start_solution(rng, S.degrees(ps), P)[None].repeat(3, 0)
+    xs[:, :, 0, 0] += 1e-3 * rng.standard_normal((3, ps.n))
+    ts = np.array([0.125, 0.5, 0.875])
+    sysd = H.System(ps)
+    xd = dev(xs)
+    norms, status = H.newton_step(sysd, xd, gamma=gam, t=dev(ts), relax_k=k)
+    xg, norms = host(xd), host(norms)
+    for q in range(3):
+        h, Jh = O.eval_h(ps, g, gam, k, float(ts[q]), xs[q])
+        rc, xo, no = O.newton_step(ps, g, gam, k, float(ts[q]), xs[q])
+        assert rc == 0
+        assert abs(norms[q, 0] - no[0]) <= 1e-14 * no[0]
+        kappa = np.linalg.cond(lead_complex(Jh).T)
+        tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
+        assert np.abs(limb_diff(xg[q], xo)).max() <= tol * no[1]
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_track_relaxation_parity(H, k):
+    """Tracking with (1 - t)^k and t^k: the oracle's decisions and endpoint."""
+    P = 2
+    ok = 0
+    for seed in (0, 3, 6):
+        ps = S.small_track_system(seed, P)
+        g = O.total_degree_start(ps)
+        gam = S.random_unit_gamma(S.rng_for(7, 60 + seed), P)
+        x0 = S.ones_point(ps.n, P)
+        sysd = H.System(ps)
+        xg, res = H.track_paths(sysd, gam, dev(x0[None]), relax_k=k, max_steps=600)
+        xg, res = host(xg)[0], res[0]
+        xo, r = O.track(ps, g, gam, k, x0, max_steps=600)
+        assert (res["status"], res["steps"], res["accepted"], res["newton_iters"]) == \
+            (r.status, r.steps, r.accepted, r.newton_iters), seed
+        assert (res["end_status"], res["end_iters"]) == (r.end_status, r.end_iters)
+        if r.status == O.OK and r.end_status == O.OK:
+            _endpoint_close(ps, xg, xo, res["res_norm"], r.res_norm, P)
+            ok += 1
+    assert ok >= 1
+
+
+def _endpoint_close(ps, xg, xo, res_g, res_o, P):
+    """Two refined roots of one regular solution: each within ||J^-1|| ||h||
+    of it, plus 16 n kappa u |x| for the solves."""
+    _, J = O.eval_jac(ps, xo)
+    Jc = lead_complex(J).T
+    kappa = np.linalg.cond(Jc)
+    jinv = np.abs(np.linalg.inv(Jc)).sum(axis=1).max()
+    scale = max(1.0, np.abs(lead_complex(xo)).max())
+    bound = 2.0 * jinv * (res_g + res_o) + max(GATE[P], 16 * ps.n * kappa * UNIT[P]) * scale
+    assert np.abs(limb_diff(xg, xo)).max() <= bound
+
+
+# ---------------------------------------------------------------------------
+# the predictor of degree 2..4 (Section 3.1)
+# ---------------------------------------------------------------------------
+
+def _line_homotopy(P, n=3):
+    cs = np.zeros((n, 2, P))
+    cs[:, 0, 0] = -1.0
+    cs[:, 1, 0] = 2.0
+    f = S.diagonal_power_system(cs, 1, P)
+    gam = np.zeros((2, P))
+    gam[0, 0] = 1.0
+    return f, gam, S.ones_point(n, P)
+
+
+@pytest.mark.parametrize("order", [1, 2, 4])
+def test_track_line_schedule(H, order):
+    """The straight-line paths of x - c from x - 1 (gamma = 1): every
+    extrapolation of degree >= 1 is exact, so the counts are those derived
+    by hand from Fig. 3 (three rejections at max_eq_val = 1/64, then
+    doubling from the fourth success, capped at max_dt, the last trial
+    clipped at 1): 23 steps, 20 accepted, 24 evaluations."""
+    P = 2
+    f, gam, x0 = _line_homotopy(P)
+    sysd = H.System(f)
+    xg, res = H.track_paths(sysd, gam, dev(x0[None]), predictor_order=order,
+                            max_eq_val=1.0 / 64)
+    r = res[0]
+    assert (r["status"], r["steps"], r["accepted"], r["newton_iters"]) == (H.OK, 23, 20, 24)
+    assert r["t"] == 1.0
+    xo, ro = O.track(f, O.total_degree_start(f), gam, 1, x0, predictor_order=order,
+                     max_eq_val=1.0 / 64)
+    assert _bitwise_equal(host(xg)[0], xo) or np.abs(limb_diff(host(xg)[0], xo)).max() <= 1e-30
+
+
+@pytest.mark.parametrize("order", [2, 3, 4])
+@pytest.mark.parametrize("P", [2, 4])
+def test_track_predictor_order_parity(H, order, P):
+    """Random small systems tracked with extrapolation of degree 2..4: the
+    predicted points are elementwise arithmetic (bitwise the oracle's for
+    equal inputs), the corrector within its tolerance, so status and step
+    counts equal the oracle's; converged endpoints within the bound."""
+    for seed in (0, 5):
+        ps = S.small_track_system(seed, P)
+        g = O.total_degree_start(ps)
+        gam = S.random_unit_gamma(S.rng_for(7, 80 + seed), P)
+        x0 = S.ones_point(ps.n, P)
+        sysd = H.System(ps)
+        xg, res = H.track_paths(sysd, gam, dev(x0[None]), predictor_order=order, max_steps=500)
+        xg, res = host(xg)[0], res[0]
+        xo, r = O.track(ps, g, gam, 1, x0, predictor_order=order, max_steps=500)
+        assert (res["status"], res["steps"], res["accepted"], res["newton_iters"]) == \
+            (r.status, r.steps, r.accepted, r.newton_iters), (seed, order)
+        if r.status == O.OK and r.end_status == O.OK:
+            _endpoint_close(ps, xg, xo, res["res_norm"], r.res_norm, P)
+
+
+def test_batch_predictor_order_matches_tracker(H):
+    """The slot-table batch with extrapolation of degree 3 gives bitwise the
+    single-system tracker's results (graph and persistent forms)."""
+    P = 2
+    cases = []
+    for seed in (1, 4):
+        ps = S.small_track_system(seed, P)
+        cases.append((ps, S.random_unit_gamma(S.rng_for(7, 90 + seed), P), S.ones_point(ps.n, P)))
+    systems = [H.System(ps) for ps, _, _ in cases]
+    alone = []
+    for (ps, gam, x0), sd in zip(cases, systems):
+        xo, r = H.track_paths(sd, gam, dev(x0[None]), predictor_order=3, max_steps=300)
+        alone.append((host(xo)[0], r[0]))
+    maxs = max(sd.info().nslots for sd in systems)
+    for persistent in (False, True):
+        bt = H.Batch(P, capacity=2, max_n=8, max_nslots=maxs, persistent=persistent,
+                     predictor_order=3, max_steps=300)
+        for slot, ((ps, gam, x0), sd) in enumerate(zip(cases, systems)):
+            bt.add(slot, sd, gam, dev(x0))
+        bt.run()
+        for slot, (ps, _, _) in enumerate(cases):
+            x, r = bt.result(slot, ps.n)
+            assert np.array_equal(host(x), alone[slot][0]) and r.tobytes() == alone[slot][1].tobytes()
+        bt.free()
+
+
+def test_predictor_order_rejected(H):
+    ps = S.small_track_system(0, 2)
+    sysd = H.System(ps)
+    gam = S.random_unit_gamma(S.rng_for(7, 1), 2)
+    with pytest.raises(H.HcnError):
+        H.track_paths(sysd, gam, dev(S.ones_point(8, 2)[None]), predictor_order=5)
+
+
+# ---------------------------------------------------------------------------
+# QD tracking of random systems
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("seed", [0, 3, 6])
+def test_track_small_system_parity_qd(H, seed):
+    P = 4
+    ps = S.small_track_system(seed, P)
+    g = O.total_degree_start(ps)
+    gam = S.random_unit_gamma(S.rng_for(0, 100 + seed), P)
+    x0 = S.ones_point(ps.n, P)
+    sysd = H.System(ps)
+    xg, res = H.track_paths(sysd, gam, dev(x0[None]), max_steps=400)
+    xg, res = host(xg)[0], res[0]
+    xo, r = O.track(ps, g, gam, 1, x0, max_steps=400)
+    assert (res["status"], res["steps"], res["accepted"], res["newton_iters"]) == \
+        (r.status, r.steps, r.accepted, r.newton_iters)
+    assert (res["end_status"], res["end_iters"]) == (r.end_status, r.end_iters)
+    if r.status == O.OK and r.end_status == O.OK:
+        _endpoint_close(ps, xg, xo, res["res_norm"], r.res_norm, P)
+
+
+# ---------------------------------------------------------------------------
+# overdetermined Newton (N > n): least squares through the same MGS
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_newton_overdetermined(H, P):
+    """N = 14 equations in n = 9 unknowns with a planted common root: one
+    Gauss-Newton step matches the oracle's within the solve bound, and the
+    device corrector converges to the root."""
+    rng = S.rng_for(7, 120 + P)
+    base = S.random_system(rng, 14, 9, (3, 6), (1, 3), (1, 2), P)
+    root = S.random_unit_point(rng, 9, P)
+    ps = M.planted_constant_terms(base, root)
+    xs = root[None].repeat(2, 0).copy()
+    xs[:, :, 0, 0] += 1e-5 * rng.standard_normal((2, 9))
+    sysd = H.System(ps)
+    xd = dev(xs)
+    norms, status = H.newton_step(sysd, xd)
+    xg = host(xd)
+    assert np.all(host(status) == 0)
+    for q in range(2):
+        rc, xo, no = O.newton_step(ps, None, None, 1, 1.0, xs[q])
+        assert rc == 0
+        _, J = O.eval_jac(ps, xs[q])
+        kappa = np.linalg.cond(lead_complex(J).T)
+        tol = max(GATE[P], 16 * ps.N * kappa * UNIT[P])
+        assert np.abs(limb_diff(xg[q], xo)).max() <= tol * no[1]
+    xd = dev(xs)
+    st, it, nm = H.newton(sysd, xd, max_iter=8, tol_res=GATE[P], tol_dx=GATE[P])
+    assert np.all(host(st) == 0)
+    err = np.abs(limb_diff(host(xd), root[None])).max()
+    assert err <= 1e3 * GATE[P]
+
+
+def test_track_needs_square(H):
+    """The total-degree start system needs N == n: tracking an
+    overdetermined system is refused before anything runs."""
+    rng = S.rng_for(7, 130)
+    ps = S.random_system(rng, 6, 4, 3, 2, (1,), 2)
+    sysd = H.System(ps)
+    with pytest.raises(H.HcnError):
+        H.track_paths(sysd, S.random_unit_gamma(rng, 2), dev(S.ones_point(4, 2)[None]))
+
+
+# ---------------------------------------------------------------------------
+# a system of the 64-system batch's shape through the slot-table batch
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batch_large_system_one_newton_step(H, mixed):
+    """n = 96, 64 monomials per equation of 12 variables, exponents 1..3
+    (the largest shape of the batched workload): one predictor-corrector
+    step of one corrector iteration (tol_dx = 1e300 accepts it, max_steps = 0
+    ends the path at the next step) leaves x_acc = x0 + dx from the start
+    point at t = max_dt.  Plain: dx matches the oracle's Newton step on the
+    homotopy within the solve bound.  Mixed: the FP64 Jacobian and solve give
+    dx within 16 n kappa 2^-53 |dx| of it."""
+    P = 2
+    rng = S.rng_for(7, 140)
+    ps = S.random_system(rng, 96, 96, 64, 12, (1, 2, 3), P)
+    g = O.total_degree_start(ps)
+    gam = S.random_unit_gamma(rng, P)
+    x0 = S.start_solution(rng, S.degrees(ps), P)
+    sysd = H.System(ps)
+    dt = 2.0 ** -4
+    bt = H.Batch(P, capacity=2, max_n=96, max_nslots=sysd.info().nslots, mixed=mixed,
+                 max_iter=1, tol_res=1e-300, tol_dx=1e300, max_eq_val=1e300, max_steps=0)
+    bt.add(1, sysd, gam, dev(x0))
+    bt.run()
+    x, r = bt.result(1, ps.n)
+    bt.free()
+    assert r["status"] == H.MAX_STEPS and r["accepted"] == 1 and r["t"] == dt
+    xg = host(x)
+    rc, xo, no = O.newton_step(ps, g, gam, 1, dt, x0)
+    assert rc == 0
+    h, Jh = O.eval_h(ps, g, gam, 1, dt, x0)
+    kappa = np.linalg.cond(lead_complex(Jh).T)
+    u = 2.0 ** -53 if mixed else UNIT[P]
+    tol = max(GATE[P], 16 * ps.n * kappa * u)
+    assert np.abs(limb_diff(xg, xo)).max() <= tol * no[1]
+
+
+# ---------------------------------------------------------------------------
+# systems freed by their owner while still in use
+# ---------------------------------------------------------------------------
+
+def test_batch_keeps_freed_system(H):
+    """A system freed by its owner while its path is in a batch stays alive
+    (the batch holds a reference); a system loaded afterwards -- possibly at
+    the same address -- gets its own entry, and both paths give the results
+    they give alone."""
+    P = 2
+    cases = []
+    for seed in (1, 4):
+        ps = S.small_track_system(seed, P)
+        cases.append((ps, S.random_unit_gamma(S.rng_for(7, 150 + seed), P), S.ones_point(ps.n, P)))
+    alone = []
+    for ps, gam, x0 in cases:
+        sd = H.System(ps)
+        xo, r = H.track_paths(sd, gam, dev(x0[None]), max_steps=200)
+        alone.append((host(xo)[0], r[0]))
+        sd.free()
+    sa = H.System(cases[0][0])
+    maxs = sa.info().nslots + 64
+    bt = H.Batch(P, capacity=2, max_n=8, max_nslots=maxs, max_systems=1, max_steps=200)
+    bt.add(0, sa, cases[0][1], dev(cases[0][2]))
+    bt._keep[0] = (None, bt._keep[0][1])
+    sa.free()           # the owner's reference goes; the batch keeps its own
+    bt.step(3)
+    bt.release(0)       # no slot uses the first system any more
+    sb = H.System(cases[1][0])
+    bt.add(1, sb, cases[1][1], dev(cases[1][2]))   # max_systems = 1: collects the first
+    sb.free()
+    bt.run()
+    x, r = bt.result(1, cases[1][0].n)
+    assert np.array_equal(host(x), alone[1][0]) and r.tobytes() == alone[1][1].tobytes()
+    # and the first system, re-added from a fresh load, tracks as alone
+    sa2 = H.System(cases[0][0])
+    bt.release(1)
+    bt.add(0, sa2, cases[0][1], dev(cases[0][2]))
+    bt.run()
+    x, r = bt.result(0, cases[0][0].n)
+    assert np.array_equal(host(x), alone[0][0]) and r.tobytes() == alone[0][1].tobytes()
+    bt.free()
+    sa2.free()
+
+
+def test_server_keeps_freed_system(H):
+    """Requests whose systems are freed by their owner right after
+    submission are still served, with the results they give alone."""
+    P = 2
+    cases = []
+    for seed in (2, 5, 7):
+        ps = S.small_track_system(seed, P)
+        cases.append((ps, S.random_unit_gamma(S.rng_for(7, 170 + seed), P), S.ones_point(ps.n, P)))
+    alone = []
+    for ps, gam, x0 in cases:
+        sd = H.System(ps)
+        xo, r = H.track_paths(sd, gam, dev(x0[None]), max_steps=200)
+        alone.append((host(xo)[0], r[0]))
+        sd.free()
+    probe = H.Batch(2, 1, 8, 4096)
+    per = probe.device_bytes()
+    probe.free()
+    srv = H.Server(int(per * 2 / 0.5), max_n=8, max_nslots=4096, qd_share=0.5, steps_per_round=4,
+                   max_steps=200)
+    for rid, (ps, gam, x0) in enumerate(cases):
+        sd = H.System(ps)
+        srv.submit(rid, sd, gam, x0, srv.now())
+        sd.free()
+    got = {}
+    import time
+    deadline = time.time() + 60
+    while len(got) < len(cases) and time.time() < deadline:
+        srv.pump()
+        while True:
+            r = srv.fetch()
+            if r is None:
+                break
+            got[r[0]] = r
+    srv.free()
+    assert len(got) == len(cases)
+    for rid in range(len(cases)):
+        _, xo, res, _, _, _ = got[rid]
+        assert np.array_equal(xo, alone[rid][0]) and res.tobytes() == alone[rid][1].tobytes()

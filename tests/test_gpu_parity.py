@@ -392,7 +392,29 @@ def test_newton_step_homotopy(H, P):
         assert np.abs(limb_diff(xg[q], xo)).max() <= tol * max(no[1], 1e-300)
 
 
+def _iterate_bound(ps, g, gam, t, x0, iters, P):
+    """Bound on the difference between two runs of `iters` Newton iterations
+    from x0 whose solves are each backward stable: every solve may differ by
+    16 n kappa u |dx| (normwise), kappa taken at each iterate of the oracle's
+    run; the differences add up (near a regular root the Newton map shrinks
+    them further).  Returns sum_k max(GATE, 16 n kappa_k u) |dx_k| plus GATE
+    for the last update's rounding."""
+    x = x0.copy()
+    total = 0.0
+    for _ in range(iters):
+        h, Jh = O.eval_h(ps, g, gam, 1, t, x)
+        kappa = np.linalg.cond(lead_complex(Jh).T)
+        rc, x, no = O.newton_step(ps, g, gam, 1, t, x)
+        if rc:
+            break
+        total += max(GATE[P], 16 * ps.n * kappa * UNIT[P]) * no[1]
+    return total + GATE[P] * max(1.0, np.abs(lead_complex(x)).max())
+
+
 def test_newton_fig2_decisions(H):
+    """Fig. 2 on the device takes the oracle's decisions (status and
+    evaluations) over a range of distances from the path; the iterates agree
+    within the bound of _iterate_bound for the updates actually applied."""
     P = 2
     ps = S.small_track_system(3, P)
     g = O.total_degree_start(ps)
@@ -411,7 +433,9 @@ def test_newton_fig2_decisions(H):
     for q in range(B):
         xo, r = O.newton(ps, g, gam, 1, float(ts[q]), xs[q], max_iter=4)
         assert status[q] == r.status and iters[q] == r.iters, (q, status[q], r.status)
-        assert np.abs(limb_diff(xg[q], xo)).max() <= 1e-20 * max(1.0, np.abs(lead_complex(xo)).max())
+        # an upper bound: one update per evaluation
+        bound = _iterate_bound(ps, g, gam, float(ts[q]), xs[q], r.iters, P)
+        assert np.abs(limb_diff(xg[q], xo)).max() <= bound, q
 
 
 # ---------------------------------------------------------------------------
@@ -458,10 +482,23 @@ def test_track_small_system_parity(H, seed):
     assert res["status"] == r.status
     assert (res["steps"], res["accepted"], res["newton_iters"]) == (r.steps, r.accepted, r.newton_iters)
     assert res["end_status"] == r.end_status and res["end_iters"] == r.end_iters
-    if r.status == O.OK:
-        scale = max(1.0, np.abs(lead_complex(xo)).max())
-        tol = 1e-26 if r.end_status == O.OK else 1e-8
-        assert np.abs(limb_diff(xg, xo)).max() <= tol * scale
+    if r.status == O.OK and r.end_status == O.OK:
+        # two refined roots of the same regular solution: each is within
+        # ||J^-1|| ||h|| of the root, plus the solves' 16 n kappa u
+        _endpoint_close(ps, xg, xo, res["res_norm"], r.res_norm, P)
+
+
+def _endpoint_close(ps, xg, xo, res_g, res_o, P):
+    """|xg - xo| <= ||J^-1||_inf (||h(xg)|| + ||h(xo)||) + 16 n kappa u |x|,
+    J the Jacobian of f at the oracle's endpoint (double is enough for the
+    bound); the residual norms are those the refinement reported."""
+    _, J = O.eval_jac(ps, xo)
+    Jc = lead_complex(J).T
+    kappa = np.linalg.cond(Jc)
+    jinv = np.abs(np.linalg.inv(Jc)).sum(axis=1).max()
+    scale = max(1.0, np.abs(lead_complex(xo)).max())
+    bound = 2.0 * jinv * (res_g + res_o) + max(GATE[P], 16 * ps.n * kappa * UNIT[P]) * scale
+    assert np.abs(limb_diff(xg, xo)).max() <= bound
 
 
 def test_track_batch_matches_single(H):
@@ -947,8 +984,8 @@ def test_batch_split_alone_mix_and_oracle(H, P):
         assert _bitwise_equal(host(x1), host(xm)) and r1.tobytes() == rm.tobytes(), q
         xo, ro = O.track(ps, O.total_degree_start(ps), gam, 1, x0, max_steps=40)
         assert (r1["status"], r1["steps"], r1["accepted"]) == (ro.status, ro.steps, ro.accepted), q
-        scale = max(1.0, np.abs(lead_complex(xo)).max())
-        assert np.abs(limb_diff(host(x1), xo)).max() <= 1e4 * GATE[P] * scale, q
+        if ro.status == O.OK and ro.end_status == O.OK and r1["end_status"] == H.OK:
+            _endpoint_close(ps, host(x1), xo, r1["res_norm"], ro.res_norm, P)
 
 
 @pytest.mark.parametrize("mixed", [False, True])
@@ -1014,7 +1051,7 @@ def test_batch_mixed_precision_tracking(H, P):
         assert rm["status"] == H.OK and rm["end_status"] == H.OK, (q, rm)
         xp, xm = host(xp), host(xm)
         scale = max(1.0, np.abs(lead_complex(xp)).max())
-        assert np.abs(limb_diff(xm, xp)).max() <= 100 * GATE[P] * scale
+        _endpoint_close(ps, xm, xp, rm["res_norm"], rp["res_norm"], P)
         fv, _ = M.eval_system(ps, M.vec(xm))
         assert max(abs(v) for v in fv) <= 100 * GATE[P] * scale ** 6
         ok += 1

@@ -124,9 +124,10 @@ def test_fig3_branches():
     h.coef[0, 0, 0] = np.nan
     _, r = O.track(h, O.total_degree_start(h), gam, 1, x0)
     assert r.status == O.NAN
-    # halving and doubling: at least one failure and the steps add up
-    xo, r = O.track(f, g, gam, 1, x0, max_dt=0.5)
-    assert r.steps >= r.accepted
+    # the step limit counts rejected steps too (the schedule itself is
+    # pinned on the linear paths below)
+    _, r = O.track(f, g, gam, 1, x0, max_dt=0.5, max_steps=3)
+    assert r.status == O.MAX_STEPS and r.steps == 4
 
 
 def test_track_small_system_roots_verified():
@@ -147,3 +148,151 @@ def test_track_small_system_roots_verified():
             assert max(abs(v) for v in fv) <= 1e-27
             ok += 1
     assert ok >= 2
+
+
+# ---------------------------------------------------------------------------
+# The step-size schedule of Fig. 3 on paths whose course is known exactly.
+#
+# With gamma = 1, g_i = x_i - 1 and f_i = x_i - c_i the homotopy
+# h = (1 - t)(x - 1) + t (x - c) is x - (1 + t (c - 1)): every path is the
+# straight line x(t) = 1 + t (c - 1) and J = 1.  Consequences used below:
+#  * the constant prediction of the first step has residual t |1 - c|
+#    (infinity norm of the leading limbs), and one Newton iteration from any
+#    point lands on the line (up to DD rounding, ~1e-32);
+#  * from the second accepted point on, extrapolation of any degree >= 1
+#    through accepted points reproduces the line, so each later corrector
+#    succeeds at its first evaluation.
+# c = -1 + 2i gives |1 - c|_inf = 2.  The expected rows are written out by
+# hand from the rules of Fig. 3: halve dt on a failure, count successes and
+# double dt (up to max_dt) at every success once more than two are counted,
+# t = min(1, t + dt).
+# ---------------------------------------------------------------------------
+
+def _line_homotopy(P, n=2):
+    cs = np.zeros((n, 2, P))
+    cs[:, 0, 0] = -1.0
+    cs[:, 1, 0] = 2.0
+    f = S.diagonal_power_system(cs, 1, P)
+    g = O.total_degree_start(f)
+    gam = np.zeros((2, P))
+    gam[0, 0] = 1.0
+    return f, g, gam, S.ones_point(n, P), cs
+
+
+@pytest.mark.parametrize("order", [1, 2, 4])
+def test_schedule_line_all_accepted(order):
+    """Every step succeeds: 16 steps of max_dt = 1/16; 2 evaluations at the
+    first (constant prediction, one solve, then a residual at rounding
+    level), 1 at each later one (exact extrapolation)."""
+    f, g, gam, x0, cs = _line_homotopy(2)
+    xo, r, rows = O.track(f, g, gam, 1, x0, trace=True, predictor_order=order)
+    assert r.status == O.OK and r.t == 1.0
+    assert r.steps == 16 and r.accepted == 16 and r.newton_iters == 17
+    assert [tuple(row) for row in rows] == \
+        [(k / 16, 1 / 16, 1.0, 2.0 if k == 1 else 1.0) for k in range(1, 17)]
+    for i in range(2):
+        assert abs(M.mp_complex(xo[i]) - M.mp_complex(cs[i])) <= 1e-30
+
+
+EXPECTED_FORCED = (
+    # trial t, dt, accepted, evaluations
+    [(1 / 16, 1 / 16, 0, 1),      # residual 1/8 > max_eq_val = 1/64: diverged
+     (1 / 32, 1 / 32, 0, 1),      # 1/16 > 1/64
+     (1 / 64, 1 / 64, 0, 1),      # 1/32 > 1/64
+     (1 / 128, 1 / 128, 1, 2),    # 1/64 is not above it: solve, then converged
+     (2 / 128, 1 / 128, 1, 1),    # second success, dt unchanged
+     (3 / 128, 1 / 128, 1, 1),    # third success: dt doubles after it
+     (5 / 128, 2 / 128, 1, 1),
+     (9 / 128, 4 / 128, 1, 1),
+     (17 / 128, 8 / 128, 1, 1)]   # dt reaches max_dt = 1/16 and stays
+    + [((17 + 8 * q) / 128, 8 / 128, 1, 1) for q in range(1, 14)]
+    + [(1.0, 8 / 128, 1, 1)])     # 129/128 clipped to 1
+
+
+@pytest.mark.parametrize("order", [1, 3])
+def test_schedule_line_forced_failures(order):
+    """max_eq_val = 1/64 rejects the first three trials (halving dt each
+    time); then the success count doubles dt from the fourth success on,
+    capped at max_dt, and the last trial is clipped at t = 1."""
+    f, g, gam, x0, cs = _line_homotopy(2)
+    xo, r, rows = O.track(f, g, gam, 1, x0, trace=True, predictor_order=order,
+                          max_eq_val=1.0 / 64)
+    got = [tuple(float(v) for v in row) for row in rows]
+    assert got == [tuple(float(v) for v in e) for e in EXPECTED_FORCED]
+    assert r.status == O.OK and r.steps == len(EXPECTED_FORCED)
+    assert r.accepted == len(EXPECTED_FORCED) - 3
+    assert r.newton_iters == sum(e[3] for e in EXPECTED_FORCED)
+
+
+def test_schedule_line_step_too_small():
+    """With min_dt = 1/32 the second halving (to 1/64) ends the path."""
+    f, g, gam, x0, _ = _line_homotopy(2)
+    _, r, rows = O.track(f, g, gam, 1, x0, trace=True, max_eq_val=1.0 / 64, min_dt=1.0 / 32)
+    assert r.status == O.STEP_TOO_SMALL and r.steps == 2 and r.t == 0.0
+    assert [tuple(row[:3]) for row in rows] == [(1 / 16, 1 / 16, 0.0), (1 / 32, 1 / 32, 0.0)]
+
+
+def test_schedule_line_corrector_budget():
+    """max_iter = 1: the first trial's prediction (x = 1, residual 2t) fails
+    until 2t < tol_res; tol_res = 1/256 accepts t = 1/1024 (residual 1/512)
+    after rejecting 1/16 .. 1/512, seven halvings."""
+    f, g, gam, x0, _ = _line_homotopy(2)
+    _, r, rows = O.track(f, g, gam, 1, x0, trace=True, max_iter=1, tol_res=1.0 / 256,
+                         tol_dx=1e-300, max_steps=8)
+    assert [tuple(row[:3]) for row in rows[:8]] == \
+        [(2.0 ** -e, 2.0 ** -e, 0.0) for e in range(4, 10)] + [(2.0 ** -10, 2.0 ** -10, 1.0)] \
+        + [(2.0 ** -9, 2.0 ** -10, 0.0)]
+    assert r.status == O.MAX_STEPS
+
+
+# ---------------------------------------------------------------------------
+# The predictor (Section 3.1): the interpolating polynomial of degree d
+# through the last d + 1 accepted points, at the trial t.
+# ---------------------------------------------------------------------------
+
+def _poly_points(rng, P, deg, ts, n=3):
+    """Values at ts of n random complex polynomials of degree deg (coefficients
+    rounded to P limbs), and the polynomials (mpmath coefficients)."""
+    coefs = [[M.mp_complex(S.unit_complex(rng.uniform(0, 6.28, 1), P)[0]) * (j + 1)
+              for j in range(deg + 1)] for _ in range(n)]
+    xs = np.zeros((len(ts), n, 2, P))
+    for j, t in enumerate(ts):
+        for i in range(n):
+            v = sum(c * mpmath.mpf(t) ** q for q, c in enumerate(coefs[i]))
+            xs[j, i] = M.complex_limbs(v, P)
+    return xs, coefs
+
+
+@pytest.mark.parametrize("P", [2, 4])
+@pytest.mark.parametrize("deg", [0, 1, 2, 3, 4])
+def test_predictor_reproduces_polynomials(P, deg):
+    """Interpolation of degree d is exact on polynomials of degree <= d: the
+    prediction matches the polynomial at t within the rounding of the data
+    and of the weights."""
+    rng = S.rng_for(6, 50 + 10 * P + deg)
+    ts = [0.5 - q / 16 for q in range(deg + 1)]   # newest first, dyadic
+    t = 0.5 + 1 / 16
+    for data_deg in range(deg + 1):
+        xs, coefs = _poly_points(rng, P, data_deg, ts)
+        out = O.predict(P, ts, xs, t)
+        for i in range(3):
+            ref = sum(c * mpmath.mpf(t) ** q for q, c in enumerate(coefs[i]))
+            assert abs(M.mp_complex(out[i]) - ref) <= 1e3 * TOL[P] * max(1, abs(ref))
+
+
+def test_predictor_degree_matters():
+    """A quadratic path is not reproduced by the secant (degree 1) but is by
+    degree 2; the secant value is the closed form x1 + (t - t1)/(t1 - t0) (x1 - x0)."""
+    rng = S.rng_for(6, 90)
+    ts = [0.25, 0.125, 0.0]
+    xs, coefs = _poly_points(rng, 2, 2, ts)
+    t = 0.375
+    sec = O.predict(2, ts[:2], xs[:2], t)
+    quad = O.predict(2, ts, xs, t)
+    for i in range(3):
+        ref = sum(c * mpmath.mpf(t) ** q for q, c in enumerate(coefs[i]))
+        x1, x0 = M.mp_complex(xs[0, i]), M.mp_complex(xs[1, i])
+        secant = x1 + (mpmath.mpf(t) - ts[0]) / (mpmath.mpf(ts[0]) - ts[1]) * (x1 - x0)
+        assert abs(M.mp_complex(sec[i]) - secant) <= 1e-29
+        assert abs(M.mp_complex(quad[i]) - ref) <= 1e-29
+        assert abs(secant - ref) > 1e-6
