@@ -149,9 +149,17 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A_dev, double *b_dev,
  * trailing matrix re-read every step), 4 tiled (Section 1: right-looking
  * over panels of T columns, each panel factored by one workgroup with its
  * columns in registers, then one launch applies the panel to every later
- * column, held in registers: 2 ceil(n/T) launches).  1 and 4 differ from 2
- * only by the rounding of their reductions.  4 falls back to 2 when
- * N > 512 (DD, FP64) or N > 256 (QD).  EINVAL outside {0, 1, 2, 4}. */
+ * column, held in registers: 2 ceil(n/T) launches), 5 pipelined (one
+ * cooperative launch: the columns stay in the LDS of persistent workgroups,
+ * column j in workgroup j mod G; the owner of a column publishes q_k in
+ * place with a flag as soon as it is projected and normalised, and every
+ * workgroup applies the q_k in order to its own later columns, the next
+ * column first).  1 and 4 differ from 2 only by the rounding of their
+ * reductions; 5 gives the bits of 2.  4 falls back to 2 when N > 512 (DD,
+ * FP64) or N > 256 (QD); 5 falls back to 2 when the columns of one
+ * workgroup do not fit its LDS or the workgroups cannot all be resident.
+ * A problem whose pipelined solve could not finish (a bounded wait ran
+ * out) reports HCN_EDEVICE in its status.  EINVAL outside {0, 1, 2, 4, 5}. */
 int hcn_set_mgs_variant(int variant);
 
 /* Panel width T of variant 4 (process-wide), 1 <= T <= 16; default 16.

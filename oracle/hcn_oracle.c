@@ -811,6 +811,10 @@ int ora_mgs_solve(int P, int N, int n, double *A, double *b, double *dx, double 
         Rl[(size_t)k * n + k].re = rkk;
         for (i = 0; i < N; i++)
             c_store(P, c_scale(P, inv[k], c_load(P, ak + i * W)), ak + i * W);
+        /* the columns j > k are independent of each other: large problems
+         * spread them over threads (each column's operations, and so its
+         * bits, are those of the serial loop) */
+#pragma omp parallel for private(i) schedule(static) if ((size_t)N * (size_t)(n - k) >= 65536)
         for (j = k + 1; j <= n; j++) {
             double *aj = ACOL(j);
             cc r = c_zero();

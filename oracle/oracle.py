@@ -25,7 +25,7 @@ OP = dict(add=0, sub=1, mul=2, div=3, sqrt=4, mul_d=5,
           cadd=10, csub=11, cmul=12, cmul_conj=13, cnorm2=14, cscale=15,
           two_sum=20, fast_two_sum=21, two_prod=22)
 
-CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99"]
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-std=c99", "-fopenmp"]
 
 
 def build(force: bool = False) -> str:

@@ -75,7 +75,11 @@ struct Workspace {
     }
 };
 
-int g_mgs_variant = 0;  // 0 auto, 1 workgroup per problem, 2 right-looking, 4 tiled
+int g_mgs_variant = 0;  // 0 auto, 1 workgroup per problem, 2 right-looking, 4 tiled, 5 pipelined
+
+// integers of an MGS workspace: per problem a status word, counters, and
+// the column flags of the pipelined variant
+size_t mgs_ints(int B, int n) { return (size_t)2 * B + 1 + (size_t)B * (n + 1); }
 size_t g_chunk_bytes = 0;  // 0: every launch covers the whole batch
 
 // the MGS variant for B problems with n unknowns
@@ -466,7 +470,7 @@ NewtonWs carve_newton(C &c, const SysView &v, int B) {
     w.inv = c.template take<double>((size_t)B * v.n * v.P);
     w.dx = c.template take<double>((size_t)B * v.n * W);
     w.st = c.template take<PathState>((size_t)B);
-    w.ints = c.template take<int>((size_t)2 * B + 1);
+    w.ints = c.template take<int>(mgs_ints(B, v.n));
     return w;
 }
 
@@ -642,7 +646,7 @@ size_t hcn_mgs_ws_bytes(int B, int N, int n, int P) {
     Carver c(nullptr);
     c.take<double>((size_t)B * (n + 1) * n * 2 * P);
     c.take<double>((size_t)B * n * P);
-    c.take<int>((size_t)2 * B + 1);
+    c.take<int>(mgs_ints(B, n));
     return c.off;
 }
 
@@ -661,7 +665,7 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A, double *b, double *dx, 
     Carver c(wsp.ptr);
     double *Rw = c.take<double>((size_t)B * (n + 1) * n * 2 * P);
     double *inv = c.take<double>((size_t)B * n * P);
-    int *ints = c.take<int>((size_t)2 * B + 1);
+    int *ints = c.take<int>(mgs_ints(B, n));
     const long W = 2 * P;
     MgsArgs a = {};
     a.B = B;
@@ -861,7 +865,7 @@ MixedWs carve_mixed(C &c, const SysView &v, int B) {
     w.inv64 = c.template take<double>((size_t)B * v.n);
     w.dx64 = c.template take<double>((size_t)B * v.n * 2);
     w.st = c.template take<PathState>((size_t)B);
-    w.ints = c.template take<int>((size_t)2 * B + 1);
+    w.ints = c.template take<int>(mgs_ints(B, v.n));
     return w;
 }
 
@@ -962,8 +966,8 @@ int hcn_newton_mixed(hcn_sys sys, const double *gamma, int relax_k, int B, const
 }
 
 int hcn_set_mgs_variant(int variant) {
-    if (variant < 0 || variant > 4 || variant == 3)
-        return fail(HCN_EINVAL, "hcn_set_mgs_variant: 0, 1, 2 or 4 (3 is not available)");
+    if (variant < 0 || variant > 5 || variant == 3)
+        return fail(HCN_EINVAL, "hcn_set_mgs_variant: 0, 1, 2, 4 or 5 (3 is not available)");
     g_mgs_variant = variant;
     return HCN_OK;
 }

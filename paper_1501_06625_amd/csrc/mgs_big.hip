@@ -14,6 +14,21 @@
 // of column k+1 then also normalises it (r_{k+1,k+1}, q_{k+1}).  The
 // trailing matrix is read and written once per step.
 //
+// Pipelined (one cooperative launch): a persistent workgroup per slice of
+// columns (column j belongs to workgroup j mod G and stays in its LDS for
+// the whole factorisation).  The owner of column k normalises it and
+// publishes q_k in place in A (the column's final value) with a flag;
+// every workgroup waits for the flags in order, stages q_k in LDS and
+// projects it out of its own later columns, the next column first, so that
+// the owner of column k+1 can publish q_{k+1} while the others still work
+// on q_k (look-ahead).  The column operations are the right-looking
+// variant's (same lanes, rows, butterflies and order), so the results are
+// bitwise the same; the trailing matrix never leaves LDS and the step
+// boundaries cost a flag instead of a launch.  Waits are bounded: a wait
+// that times out (a workgroup not resident, which the cooperative launch
+// rules out) or a singular column stops every workgroup of the problem, and
+// the epilogue reports the problem as failed (HCN_EDEVICE or ESINGULAR).
+//
 // Tiled (panel width T; mgs_tiled.hpp): the columns are taken T at a time.
 // A panel launch factors columns k0..k0+T-1 in one workgroup of T
 // wavefronts, each holding one column in registers; a trailing launch gives
@@ -183,6 +198,120 @@ __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
 }
 
 // ---------------------------------------------------------------------------
+// pipelined: one cooperative launch, columns resident in LDS
+// ---------------------------------------------------------------------------
+// sing[b]: 0 running, 1 singular column, 2 a wait timed out
+constexpr int PIPE_SINGULAR = 1, PIPE_TIMEOUT = 2;
+
+// Thread 0 waits (bounded) until flags[k] is set or the problem stopped;
+// the acquire fence then makes the published column visible to the
+// workgroup.  Returns false (on every thread) when the problem stopped.
+HCN_DEV bool pipe_wait(const int *flag, int *stop_word, long spin_limit, int *s_go) {
+    if (threadIdx.x == 0) {
+        int go = 1;
+        long spins = 0;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            if (__hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+                go = 0;
+                break;
+            }
+            if (++spins > spin_limit) {
+                __hip_atomic_store(stop_word, PIPE_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                go = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        *s_go = go;
+    }
+    __syncthreads();
+    return *s_go != 0;
+}
+
+template <class R>
+__global__ __launch_bounds__(BT) void k_mgs_pipe(MgsArgs a, int *sing, int *flags, long spin_limit) {
+    constexpr int P = limbs<R>::P;
+    constexpr int W = 2 * P;
+    extern __shared__ double lds[];  // own columns [c][N][W], then q_k [N][W]
+    __shared__ cx<R> s_part[BT / 64];
+    __shared__ R s_rpart[BT / 64];
+    __shared__ R s_inv;
+    __shared__ int s_bad, s_go;
+    const int b = blockIdx.y;
+    if (!problem_live(a, b)) return;
+    const int G = gridDim.x, w = blockIdx.x, n = a.n, N = a.N;
+    const size_t cst = (size_t)N * W;
+    if (w > n) return;
+    const int mine = (n - w) / G + 1;  // columns w, w + G, ...
+    double *q = lds + (size_t)mine * cst;
+    int *flg = flags + (size_t)b * (n + 1);
+    int *stop = sing + b;
+    for (int c = 0; c < mine; ++c) {
+        const double *src = col_ptr(a, b, w + c * G);
+        for (size_t t = threadIdx.x; t < cst; t += BT) lds[(size_t)c * cst + t] = src[t];
+    }
+    __syncthreads();
+    // column j (owned, in LDS slot c), fully projected: r_jj, 1/r_jj, q_j;
+    // q_j goes to its place in A and its flag is raised.  False: singular.
+    auto publish = [&](int c) -> bool {
+        const int j = w + c * G;
+        double *aj = lds + (size_t)c * cst;
+        if (!col_normalise<R>(a, b, j, aj, s_rpart, &s_inv, &s_bad)) {
+            if (threadIdx.x == 0)
+                __hip_atomic_store(stop, PIPE_SINGULAR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __syncthreads();  // the scaled rows, written row-wise, are copied element-wise
+        double *dst = col_ptr(a, b, j);
+        for (size_t t = threadIdx.x; t < cst; t += BT) dst[t] = aj[t];
+        // the workgroup's stores complete before the barrier; the release
+        // store writes them back beyond this XCD's L2 before the flag
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(flg + j, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    };
+    bool live = true;
+    if (w == 0 && n > 0) live = publish(0);
+    for (int k = 0; k < n && live; ++k) {
+        const double *qk;
+        if (k % G == w) {
+            qk = lds + (size_t)(k / G) * cst;
+        } else {
+            // q_k is needed only while this workgroup has a column beyond k
+            if (k >= w && w + ((k - w) / G + 1) * G > n) break;
+            if (!pipe_wait(flg + k, stop, spin_limit, &s_go)) {
+                live = false;
+                break;
+            }
+            const double *src = col_ptr(a, b, k);
+            for (size_t t = threadIdx.x; t < cst; t += BT) q[t] = src[t];
+            __syncthreads();
+            qk = q;
+        }
+        // own columns j > k in increasing order (column k+1 first)
+        const int c0 = k < w ? 0 : (k - w) / G + 1;
+        for (int c = c0; c < mine && live; ++c) {
+            const int j = w + c * G;
+            double *aj = lds + (size_t)c * cst;
+            const cx<R> r = col_dot<R>(qk, aj, N, s_part);
+            if (threadIdx.x == 0)
+                cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * n + k) * W, r);
+            col_axpy<R>(qk, aj, r, N);
+            if (j == k + 1 && j < n) live = publish(c);
+        }
+        __syncthreads();  // q is staged again for the next k
+    }
+    // the projected right-hand side (column n) goes back to its place
+    if (live && n % G == w) {
+        __syncthreads();
+        const double *src = lds + (size_t)(n / G) * cst;
+        double *dst = col_ptr(a, b, n);
+        for (size_t t = threadIdx.x; t < cst; t += BT) dst[t] = src[t];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // tiled: panel and trailing launches over the bodies in mgs_tiled.hpp
 // ---------------------------------------------------------------------------
 // Panel k0..k1-1 of problem blockIdx.x; blockDim.x = 64 (k1 - k0).  The
@@ -253,7 +382,24 @@ template <class R>
 __global__ __launch_bounds__(BT) void k_mgs_finish(MgsArgs a, const int *sing) {
     const int b = blockIdx.x;
     if (!problem_live(a, b)) return;
-    mgs_epilogue<R>(problem_of(a, b), sing[b] != 0);
+    const MgsProblem p = problem_of(a, b);
+    if (sing[b] == PIPE_TIMEOUT) {
+        // a wait of the pipelined variant timed out: the factorisation is
+        // incomplete, reported as a device error of this problem
+        if (threadIdx.x == 0) {
+            if (p.status) *p.status = HCN_EDEVICE;
+            if (p.mode == MGS_NEWTON_FIG2 || p.mode == MGS_MIXED_SOLVE) {
+                p.st->c_status = HCN_EDEVICE;
+                p.st->c_active = 0;
+            }
+            if (p.mode == MGS_NEWTON_STEP && p.norms) {
+                p.norms[0] = residual_norm(p);
+                p.norms[1] = __builtin_nan("");
+            }
+        }
+        return;
+    }
+    mgs_epilogue<R>(p, sing[b] != 0);
 }
 
 __global__ void k_zero_int(int *p, int count) {
@@ -261,16 +407,59 @@ __global__ void k_zero_int(int *p, int count) {
     if (q < count) p[q] = 0;
 }
 
+// workgroups of the pipelined variant for one problem (0: it does not fit):
+// at most one per CU-slot the occupancy calculator allows with the LDS of
+// its columns, and B of them must be resident together
+template <class R>
+static int pipe_groups(const MgsArgs &a, size_t *lds_out) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return 0;
+    }
+    const size_t cst = (size_t)a.N * 2 * limbs<R>::P * sizeof(double);
+    int G = std::min(cus / std::max(a.B, 1), a.n + 1);
+    if (G < 1) return 0;
+    const int mine = a.n / G + 1;
+    const size_t lds = (size_t)(mine + 1) * cst;
+    if (lds > 160 * 1024) return 0;
+    (void)hipFuncSetAttribute((const void *)k_mgs_pipe<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mgs_pipe<R>, BT, lds) != hipSuccess ||
+        per_cu < 1)
+        return 0;
+    *lds_out = lds;
+    return G;
+}
+
+// bounded waits: about a second of polling before a wait gives up
+constexpr long PIPE_SPIN_LIMIT = 1L << 22;
+
 template <class R>
 static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s) {
-    // ints: sing[B]
+    // ints: sing[B], then (after 2B + 1) the column flags [B][n + 1]
     int *sing = ints;
-    hipLaunchKernelGGL(k_zero_int, dim3((a.B + 255) / 256), dim3(256), 0, s, ints, a.B);
+    int *flags = ints + 2 * a.B + 1;
+    size_t pipe_lds = 0;
+    const int G = variant == 5 ? pipe_groups<R>(a, &pipe_lds) : 0;
+    if (variant == 5 && G == 0) variant = 2;
+    const long nz = variant == 5 ? 2L * a.B + 1 + (long)a.B * (a.n + 1) : a.B;
+    hipLaunchKernelGGL(k_zero_int, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, ints, (int)nz);
     if (a.mode == MGS_NEWTON_FIG2)
         hipLaunchKernelGGL(k_fig2_pre, dim3((a.B + 255) / 256), dim3(256), 0, s, a);
     {
         ProfScope prof("mgs", s);
-        if (variant == 4) {
+        if (variant == 5) {
+            MgsArgs av = a;
+            long spin = PIPE_SPIN_LIMIT;
+            void *args[] = {&av, &sing, &flags, &spin};
+            const hipError_t e = hipLaunchCooperativeKernel((const void *)k_mgs_pipe<R>, dim3(G, a.B),
+                                                            dim3(BT), args, (unsigned)pipe_lds, s);
+            if (e != hipSuccess) return (int)e;
+        } else if (variant == 4) {
             launch_tiled<R>(a, sing, s);
         } else {
             hipLaunchKernelGGL(k_mgs_rl<R>, dim3(1, a.B), dim3(BT), 0, s, a, -1, sing);

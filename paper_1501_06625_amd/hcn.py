@@ -396,7 +396,7 @@ def profile_query(kernel: str):
     return ms.value, cnt.value
 
 
-MGS_AUTO, MGS_WORKGROUP, MGS_RIGHT_LOOKING, MGS_TILED = 0, 1, 2, 4
+MGS_AUTO, MGS_WORKGROUP, MGS_RIGHT_LOOKING, MGS_TILED, MGS_PIPELINED = 0, 1, 2, 4, 5
 
 
 def set_mgs_variant(variant: int) -> None:

@@ -46,3 +46,11 @@ def term_scales(ps, x):
 def random_points(rng, B, n, P):
     from paper_1501_06625_amd import systems as S
     return S.unit_complex(rng.uniform(0, 2 * np.pi, B * n), P).reshape(B, n, 2, P)
+
+
+def update_bound(tol, dx_norm, x_ref, P):
+    """Bound on |x_gpu - x_oracle| after one Newton update x + dx: the
+    solves' difference tol |dx|, plus the rounding of the sum x + dx on each
+    side (at most 2 UNIT |x|, UNIT at least three units of the last place of
+    the accurate double-word / quad-word sum)."""
+    return tol * dx_norm + 2.0 * UNIT[P] * max(1.0, float(np.abs(lead_complex(x_ref)).max()))

@@ -45,7 +45,7 @@ def test_host_side_argument_errors():
     assert lib.hcn_mgs_solve(1, 2, 3, 2, None, None, None, None, None, None, 0, None) == hcn.EINVAL
     assert lib.hcn_elementwise(99, 2, 1, None, None, None, None) == hcn.EINVAL
     assert lib.hcn_version() == 100
-    assert lib.hcn_set_mgs_variant(5) == hcn.EINVAL
+    assert lib.hcn_set_mgs_variant(6) == hcn.EINVAL
     # the column-resident variant is not available
     assert lib.hcn_set_mgs_variant(3) == hcn.EINVAL
     assert lib.hcn_set_mgs_variant(0) == hcn.OK

@@ -15,7 +15,7 @@ import pytest
 from oracle import oracle as O
 from oracle import mpref as M
 from paper_1501_06625_amd import systems as S
-from tests.gpu_util import GATE, UNIT, limb_diff, lead_complex, term_scales, random_points
+from tests.gpu_util import GATE, UNIT, limb_diff, lead_complex, term_scales, random_points, update_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -365,7 +365,7 @@ def test_newton_step_dense32(H, P):
         assert rc == 0
         kappa = _kappa_at(ps, xs[q])
         tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
-        assert np.abs(limb_diff(xg[q], xo)).max() <= tol * no[1]
+        assert np.abs(limb_diff(xg[q], xo)).max() <= update_bound(tol, no[1], xo, P)
         assert abs(norms[q, 0] - no[0]) <= 1e-14 * no[0]
         assert abs(norms[q, 1] - no[1]) <= 1e-10 * no[1]
 
@@ -531,21 +531,41 @@ def _solve_variant(H, variant, A, b):
         H.set_mgs_variant(H.MGS_AUTO)
 
 
-@pytest.mark.parametrize("P,N,n", [(2, 512, 512), (2, 300, 257), (4, 200, 200)])
-def test_mgs_big_variants_bitwise(H, P, N, n):
-    """Right-looking and column-resident variants: identical bits; the
-    one-workgroup variant within the solve tolerance."""
-    rng = np.random.default_rng(N + n + P)
-    A = _rand_matrix(rng, N, n, P)[None]
-    b = random_points(rng, 1, N, P)
-    d2, R2, s2 = _solve_variant(H, 2, A, b)
-    d3, R3, s3 = _solve_variant(H, 3, A, b)
-    assert s2[0] == 0 and s3[0] == 0
-    assert _bitwise_equal(d2, d3) and _bitwise_equal(R2, R3)
+def _solve_variant_q(H, variant, A, b):
+    """As _solve_variant, also returning Q (A overwritten) and the projected b."""
+    H.set_mgs_variant(variant)
+    try:
+        Ad, bd = dev(A), dev(b)
+        dx, R, status = H.mgs_solve(Ad, bd)
+        return host(dx), host(R), host(status), host(Ad), host(bd)
+    finally:
+        H.set_mgs_variant(H.MGS_AUTO)
+
+
+@pytest.mark.parametrize("P,N,n,B", [(2, 512, 512, 1), (2, 300, 257, 1), (4, 200, 200, 1),
+                                     (2, 700, 300, 2), (4, 96, 600, 1)])
+def test_mgs_big_variants_bitwise(H, P, N, n, B):
+    """Right-looking and pipelined variants: identical bits in dx, R, Q and
+    the projected right-hand side (the pipelined one with its columns
+    resident in LDS, one or two problems per launch, more columns than
+    workgroups, N > n); the one-workgroup variant within the solve
+    tolerance."""
+    if n > N:
+        n, N = N, n
+    rng = np.random.default_rng(N + n + P + B)
+    A = np.stack([_rand_matrix(rng, N, n, P) for _ in range(B)])
+    b = random_points(rng, B, N, P)
+    print(f"mgs variants P={P} N={N} n={n} B={B}", flush=True)
+    d2, R2, s2, Q2, b2 = _solve_variant_q(H, 2, A, b)
+    d5, R5, s5, Q5, b5 = _solve_variant_q(H, 5, A, b)
+    assert np.all(s2 == 0) and np.all(s5 == 0)
+    for u, v in ((d2, d5), (R2, R5), (Q2, Q5), (b2, b5)):
+        assert _bitwise_equal(u, v)
     d1, R1, s1 = _solve_variant(H, 1, A, b)
-    kappa = np.linalg.cond(lead_complex(A[0]).T)
-    tol = max(GATE[P], 16 * n * kappa * UNIT[P])
-    assert np.abs(limb_diff(d1, d2)).max() <= tol * np.abs(lead_complex(d2)).max()
+    for q in range(B):
+        kappa = np.linalg.cond(lead_complex(A[q]).T)
+        tol = max(GATE[P], 16 * n * kappa * UNIT[P])
+        assert np.abs(limb_diff(d1[q], d2[q])).max() <= tol * np.abs(lead_complex(d2[q])).max()
 
 
 @pytest.mark.parametrize("P,N,n,T", [(2, 300, 257, 3), (4, 200, 200, 8), (4, 256, 100, 16),
@@ -598,7 +618,7 @@ def test_mgs_big_backward_error(H):
     rng = np.random.default_rng(160)
     A = _rand_matrix(rng, n, n, P)[None]
     b = random_points(rng, 1, n, P)
-    for v in (2, 3, 4):
+    for v in (2, 4, 5):
         d, _, s = _solve_variant(H, v, A, b)
         assert s[0] == 0
         assert _backward_error(A[0], b[0], d[0]) <= GATE[P]
@@ -610,20 +630,26 @@ def test_mgs_big_singular(H):
     A = _rand_matrix(rng, 200, 200, P)[None]
     A[0, 150] = 0.0
     b = random_points(rng, 1, 200, P)
-    for v in (2, 3, 4):
+    for v in (2, 4, 5):
+        _, _, s = _solve_variant(H, v, A, b)
+        assert s[0] == H.ESINGULAR
+    # and a first column of zeros (the pipelined variant stops before any flag)
+    A[0, 0] = 0.0
+    for v in (2, 5):
         _, _, s = _solve_variant(H, v, A, b)
         assert s[0] == H.ESINGULAR
 
 
 def test_newton_step_sparse512_vs_oracle(H):
-    """The full-size sparse n = 512 Newton step (column-resident solve, the
-    configuration the benchmark times) against the oracle's plain step."""
+    """The full-size sparse n = 512 Newton step (every solve variant, the
+    configurations the benchmark times) against the oracle's plain step;
+    right-looking and pipelined bit for bit."""
     P = 2
     ps = S.sparse512_system(0, P)
     x = random_points(np.random.default_rng(12), 1, ps.n, P)
     sysd = H.System(ps)
     out = {}
-    for v in (1, 3, 4):
+    for v in (1, 2, 4, 5):
         H.set_mgs_variant(v)
         xd = dev(x)
         norms, status = H.newton_step(sysd, xd)
@@ -635,8 +661,9 @@ def test_newton_step_sparse512_vs_oracle(H):
     f, J = O.eval_jac(ps, x[0])
     kappa = np.linalg.cond(lead_complex(J).T)
     tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
-    for v in (1, 3, 4):
-        assert np.abs(limb_diff(out[v], xo)).max() <= tol * no[1], v
+    for v in (1, 2, 4, 5):
+        assert np.abs(limb_diff(out[v], xo)).max() <= update_bound(tol, no[1], xo, P), v
+    assert _bitwise_equal(out[2], out[5])
 
 
 # ---------------------------------------------------------------------------
@@ -729,7 +756,7 @@ def test_tuned_variants(H, P):
         kappa = _kappa_at(ps, xs[q])
         tol = max(GATE[P], 16 * ps.n * kappa * UNIT[P])
         for grp in (8, 32):
-            assert np.abs(limb_diff(out[(grp, 1)][q], xo)).max() <= tol * no[1]
+            assert np.abs(limb_diff(out[(grp, 1)][q], xo)).max() <= update_bound(tol, no[1], xo, P)
 
 
 def test_point_chunking_bitwise(H):

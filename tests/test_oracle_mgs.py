@@ -130,3 +130,33 @@ def test_diagonal_matrix_exact():
         assert dx[k, 0, 0] == 3.0 * 2.0 ** k / 2.0 ** (k - 2)
         assert dx[k, 1, 0] == -2.0 ** -k / 2.0 ** (k - 2)
         assert Q[k, k, 0, 0] == 1.0
+
+
+def test_threaded_columns_bitwise():
+    """Large problems spread the trailing columns of each step over threads;
+    each column sees the serial loop's operations, so Q, R and dx are the
+    serial run's bit for bit (the serial run in a child process with one
+    thread)."""
+    import os
+    import subprocess
+    import sys
+    rng = S.rng_for(9, 3)
+    N = n = 160
+    A = S.unit_complex(rng.uniform(0, 2 * np.pi, N * n), 2).reshape(n, N, 2, 2)
+    b = S.unit_complex(rng.uniform(0, 2 * np.pi, N), 2).reshape(N, 2, 2)
+    rc, dx, Q, R, _ = O.mgs_solve(2, A, b)
+    assert rc == 0
+    code = ("import sys, numpy as np; sys.path.insert(0, %r); from oracle import oracle as O; "
+            "A = np.load(sys.argv[1]); b = np.load(sys.argv[2]); rc, dx, Q, R, _ = O.mgs_solve(2, A, b); "
+            "np.save(sys.argv[3], np.concatenate([dx.ravel(), Q.ravel(), R.ravel()]))")
+    import tempfile
+    with tempfile.TemporaryDirectory() as d:
+        pa, pb, po = (os.path.join(d, f) for f in ("A.npy", "b.npy", "o.npy"))
+        np.save(pa, A)
+        np.save(pb, b)
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+        subprocess.check_call([sys.executable, "-c", code % root, pa, pb, po], env=env)
+        serial = np.load(po)
+    threaded = np.concatenate([dx.ravel(), Q.ravel(), R.ravel()])
+    assert np.array_equal(serial.view(np.uint64), threaded.view(np.uint64))
