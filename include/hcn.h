@@ -251,6 +251,26 @@ int hcn_newton_step(hcn_sys sys, const double *gamma, int relax_k, int B,
                     int32_t *status_dev, void *ws_dev, size_t ws_bytes,
                     void *stream);
 
+/* hcn_newton_step without allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc).  The same launches as hcn_newton_step, with the
+ * workspace in a fixed device array of HCN_STATIC_WS_BYTES that the
+ * library's code object holds on every GPU it runs on until the process
+ * ends.  Its address on a device is looked up once, on the first call on
+ * that device.  The call allocates nothing, creates no events (profiling
+ * is held off for it) and leaves nothing in the array that a later call
+ * relies on: no part of it must start at zero.
+ * Arguments as hcn_newton_step without ws_dev / ws_bytes; EINVAL (before any
+ * launch) when hcn_newton_ws_bytes(sys, B) exceeds HCN_STATIC_WS_BYTES
+ * (complex DD: about 107 points of the dense n = 32 system, 3 of the sparse
+ * n = 512 one).  All calls on one GPU share its array: calls whose work can overlap
+ * on the device (other host threads, or streams not ordered with each
+ * other) race on it; calls on one stream are ordered and safe. */
+#define HCN_STATIC_WS_BYTES (64u << 20)
+int hcn_newton_step_static(hcn_sys sys, const double *gamma, int relax_k, int B,
+                           const double *t_dev, double *x_dev, double *norms_dev,
+                           int32_t *status_dev, void *stream);
+
 typedef struct {
     int max_iter;       /* iterations (evaluations) at most */
     double tol_res;     /* success when ||h|| < tol_res */

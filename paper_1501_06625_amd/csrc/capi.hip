@@ -8,11 +8,13 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
 
 #include "internal.hpp"
+#include "prof.hpp"
 
 using namespace hcn;
 
@@ -715,6 +717,89 @@ int hcn_newton_step(hcn_sys sys, const double *gamma, int relax_k, int B, const 
     a.norms = norms;
     a.status = status;
     return enqueue_newton_iter(v, B, x, hom, w, nullptr, a, s);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// hcn_newton_step_static: hcn_newton_step on a fixed device workspace
+// ---------------------------------------------------------------------------
+
+// The workspace of hcn_newton_step_static, a device array of the library's
+// code object: every GPU the library runs on holds its own copy, at its own
+// address, until the process ends.  In host code its name is a host-side
+// stand-in, never a device address; kernels receive the address that
+// hipGetSymbolAddress returns for the device (static_ws below).
+static __device__ __align__(256) char scratch[HCN_STATIC_WS_BYTES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void *g_static_ws[MAX_DEVICES];  // per device, set once
+
+// the device the stream's work runs on (the current one for the null stream)
+int stream_device(hipStream_t s, int *dev) {
+    if (s) {
+        if (hipStreamGetDevice(s, dev) != hipSuccess)
+            return fail(HCN_EDEVICE, "hcn_newton_step_static: stream without a device");
+    } else if (hipGetDevice(dev) != hipSuccess) {
+        return fail(HCN_EDEVICE, "hcn_newton_step_static: no current device");
+    }
+    if (*dev < 0 || *dev >= MAX_DEVICES)
+        return fail(HCN_EDEVICE, "hcn_newton_step_static: device %d beyond the table", *dev);
+    return HCN_OK;
+}
+
+// address of the device's copy of `scratch`: looked up on the first call on
+// that device, with that device current, and kept
+int static_ws(hipStream_t s, void **out) {
+    int dev = -1;
+    int rc = stream_device(s, &dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ws[dev]) {
+        int cur = -1;
+        if (hipGetDevice(&cur) != hipSuccess)
+            return fail(HCN_EDEVICE, "hcn_newton_step_static: no current device");
+        if (cur != dev && hipSetDevice(dev) != hipSuccess)
+            return fail(HCN_EDEVICE, "hcn_newton_step_static: cannot select device %d", dev);
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return fail(HCN_EDEVICE, "hcn_newton_step_static: workspace address on device %d: %s",
+                        dev, hipGetErrorString(e));
+        g_static_ws[dev] = p;
+    }
+    *out = g_static_ws[dev];
+    return HCN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hcn_newton_step_static(hcn_sys sys, const double *gamma, int relax_k, int B,
+                           const double *t, double *x, double *norms, int32_t *status,
+                           void *stream) {
+    if (!sys) return fail(HCN_EINVAL, "hcn_newton_step_static: NULL system");
+    if (B < 0) return fail(HCN_EINVAL, "hcn_newton_step_static: negative batch");
+    const size_t need = hcn_newton_ws_bytes(sys, B);
+    if (need > (size_t)HCN_STATIC_WS_BYTES)
+        return fail(HCN_EINVAL,
+                    "hcn_newton_step_static: %d points need %zu bytes of workspace, more than "
+                    "the fixed %zu (use hcn_newton_step with a workspace of its own)",
+                    B, need, (size_t)HCN_STATIC_WS_BYTES);
+    if (B == 0) return HCN_OK;
+    hipStream_t s = (hipStream_t)stream;
+    void *ws = nullptr;
+    const int rc = static_ws(s, &ws);
+    if (rc) return rc;
+    // the launches create no profiling events either
+    ProfPause no_events;
+    return hcn_newton_step(sys, gamma, relax_k, B, t, x, norms, status, ws,
+                           (size_t)HCN_STATIC_WS_BYTES, stream);
 }
 
 int hcn_newton(hcn_sys sys, const double *gamma, int relax_k, int B, const double *t, double *x,

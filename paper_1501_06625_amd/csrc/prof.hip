@@ -17,9 +17,12 @@ std::atomic<bool> g_on{false};
 std::mutex g_mu;
 std::vector<Rec> g_recs;
 std::vector<hipEvent_t> g_pool;
+thread_local int g_paused = 0;
 }  // namespace
 
-bool prof_on() { return g_on.load(std::memory_order_relaxed); }
+bool prof_on() { return g_paused == 0 && g_on.load(std::memory_order_relaxed); }
+
+void prof_pause(bool on) { g_paused += on ? 1 : -1; }
 
 hipEvent_t prof_event() {
     std::lock_guard<std::mutex> lk(g_mu);

@@ -7,6 +7,13 @@
 namespace hcn {
 
 bool prof_on();
+// profiling held off on the calling thread while a ProfPause lives (entry
+// points that must not create events)
+void prof_pause(bool on);
+struct ProfPause {
+    ProfPause() { prof_pause(true); }
+    ~ProfPause() { prof_pause(false); }
+};
 void prof_record(const char *name, hipEvent_t start, hipEvent_t stop);
 hipEvent_t prof_event();
 

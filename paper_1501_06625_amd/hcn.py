@@ -61,7 +61,8 @@ assert PATH_RESULT_DTYPE.itemsize == 48
 # every symbol the header declares
 EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn_sys_info",
            "hcn_sys_degrees", "hcn_eval_ws_bytes", "hcn_eval_jac", "hcn_mgs_ws_bytes",
-           "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton",
+           "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton_step_static",
+           "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
            "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_set_chunk_bytes", "hcn_set_mon_uniform", "hcn_set_mon_tree", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
            "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load", "hcn_autotune",
@@ -93,6 +94,7 @@ def _load():
     lib.hcn_newton_ws_bytes.argtypes = [vp, ci]
     lib.hcn_newton_ws_bytes.restype = sz
     lib.hcn_newton_step.argtypes = [vp, vp, ci, ci, vp, vp, vp, vp, vp, sz, vp]
+    lib.hcn_newton_step_static.argtypes = [vp, vp, ci, ci, vp, vp, vp, vp, vp]
     lib.hcn_newton.argtypes = [vp, vp, ci, ci, vp, vp, ctypes.POINTER(_NewtonParams), vp, vp, vp,
                                vp, sz, vp]
     lib.hcn_track_ws_bytes.argtypes = [vp, ci]
@@ -294,6 +296,28 @@ def newton_step(sys: System, x: torch.Tensor, gamma=None, t: Optional[torch.Tens
         ws = _workspace(need, x.device)
     _check(_lib.hcn_newton_step(sys.handle, gp, relax_k, B, _ptr(t), _ptr(xb), _ptr(norms),
                                 _ptr(status), _ptr(ws), ws.numel(), _stream()))
+    if not batched:
+        return norms[0], status[0]
+    return norms, status
+
+
+# bytes of the fixed device workspace of hcn_newton_step_static
+STATIC_WS_BYTES = 64 << 20
+
+
+def newton_step_static(sys: System, x: torch.Tensor, gamma=None,
+                       t: Optional[torch.Tensor] = None, relax_k: int = 1):
+    """newton_step on the library's fixed device workspace (no allocation by
+    the library; norms and status are the caller's outputs, allocated here)."""
+    xb, batched = _batched(x, 3)
+    if not xb.is_contiguous():
+        raise ValueError("x must be contiguous (updated in place)")
+    B = xb.shape[0]
+    norms = torch.empty((B, 2), dtype=torch.float64, device=x.device)
+    status = torch.empty(B, dtype=torch.int32, device=x.device)
+    g, gp = _gamma_arg(gamma, sys.P)
+    _check(_lib.hcn_newton_step_static(sys.handle, gp, relax_k, B, _ptr(t), _ptr(xb),
+                                       _ptr(norms), _ptr(status), _stream()))
     if not batched:
         return norms[0], status[0]
     return norms, status
