@@ -18,12 +18,13 @@ Reported beside it, one object per workload:
 * sparse512: one Newton step of the sparse n = 512 system per MGS variant,
   with the bitwise comparison of the variants;
 * batch64: 4096 paths of 64 random systems in one slot-table batch (Newton
-  steps/s, paths/s of a planted-root variant tracked to completion, and the
+  steps/s, paths/s of a finite-roots variant tracked to completion, and the
   time to a residual of 1e-28 of the plain and the mixed-precision corrector);
 * serve: continuous batching of track_path requests at several arrival
   rates, with the one-at-a-time baseline on the same trace;
 * cyclic: evaluation and differentiation of the cyclic n-roots system
-  (n = 128, 352).
+  (n = 128, 352);
+* double: complex double, reverse against tree-mode monomials.
 Every GPU leg keeps a sample of its results; the CPU leg (the oracle, timed
 on this host's cores) computes their errors against the oracle: forward
 differences, normwise backward errors formed at 320 bits from the oracle's
@@ -94,6 +95,8 @@ def source_digest() -> str:
 
 B_DD = 10240
 B_QD = 2048
+# extrapolation degree of the tracked finite-roots paths (batch and serving)
+PLANTED_ORDER = 4
 
 
 def status_hist(codes) -> dict:
@@ -300,13 +303,16 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
       residual evaluations and solves counted per path on the device, flops
       per path from its own system.  These systems have no constant term, so
       most of their total-degree paths run to x = 0 or to infinity.
-    * paths_planted: the planted-root variant (a constant term per equation
-      that makes x = (1, ..., 1) a root), all 4096 paths tracked to
-      completion, end-point refinement to 1e-28 included: paths/s, status,
-      steps.
-    * newton_1e28: Newton's method from 1e-6 perturbations of the planted
-      root (64 points per system), plain against mixed precision, until the
-      residual is below 1e-28: time, iterations, distance to the root."""
+    * paths_finite: the finite-roots variant (per equation a pure power
+      x_i^{d_i} and a constant term that makes x = (1, ..., 1) a root: no
+      roots at infinity, so every total-degree path ends at a finite root),
+      all 4096 paths tracked to completion with the predictor of degree 4
+      (Section 4.2), end-point refinement to 1e-28 included: paths/s,
+      status, steps.
+    * newton_1e28: Newton's method from 1e-6 perturbations of the root
+      x = 1 of the same variant (64 points per system), plain against mixed
+      precision, until the residual is below 1e-28: time, iterations,
+      distance to the root."""
     import numpy as np
     import torch
     systems = S.batch_systems(nsys, seed=0, P=2)
@@ -375,17 +381,17 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
     for s in loaded:
         s.free()
 
-    # planted-root variant: paths to completion, and Newton to 1e-28
-    progress("batch: planted-root systems")
-    planted = [S.with_root_at_ones(ps) for ps in systems]
+    # finite-roots variant: paths to completion, and Newton to 1e-28
+    progress("batch: finite-roots systems")
+    planted = [S.with_finite_roots(ps, s) for s, ps in enumerate(systems)]
     ploaded = [hcn.System(ps) for ps in planted]
     pmax_slots = max(s.info().nslots for s in ploaded)
-    res["paths_planted"] = {}
+    res["paths_finite"] = {}
     sample = {"systems": planted, "gammas": gammas, "paths": []}
     for mode in ("plain", "mixed"):
-        progress(f"batch: planted paths to completion, {mode}")
+        progress(f"batch: paths to completion, {mode}")
         bt = hcn.Batch(2, nsys * per, max_n, pmax_slots, max_systems=nsys, mixed=(mode == "mixed"),
-                       split_n=split_n)
+                       split_n=split_n, predictor_order=PLANTED_ORDER)
         for s in range(nsys):
             for q in range(per):
                 bt.add(s * per + q, ploaded[s], gammas[s], starts[s][q])
@@ -407,11 +413,11 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
                                             "steps": int(r["steps"])})
         bt.free()
         ok = sum(1 for c in st if c == 0)
-        res["paths_planted"][mode] = {
-            "wall_s": wall, "paths_per_s": len(st) / wall, "ok": ok, "success_rate": ok / len(st),
+        res["paths_finite"][mode] = {
+            "predictor_order": PLANTED_ORDER, "wall_s": wall, "paths_per_s": len(st) / wall, "ok": ok, "success_rate": ok / len(st),
             "status": status_hist(st), "steps_median": float(np.median(stp)),
             "ok_and_refined_to_1e-28": int(sum(1 for c, e in zip(st, ends) if c == 0 and e == 0))}
-    progress("batch: Newton to 1e-28 from perturbed planted roots")
+    progress("batch: Newton to 1e-28 from perturbed roots")
     rngp = S.rng_for(3, 4242)
     out = {}
     for mode in ("plain", "mixed"):
@@ -452,15 +458,19 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
     return res
 
 
-def serve_leg(hcn, S, dev, pool: int = 64, burst: int = 192, per_rate: int = 192,
-              rates=(0.5, 0.8, 0.95), serial_sample: int = 16, literal_burst: int = 96,
+def serve_leg(hcn, S, dev, pool: int = 64, burst: int = 128, per_rate: int = 96,
+              rates=(0.5, 0.8, 0.95), serial_sample: int = 12, literal_burst: int = 64,
               literal_max_steps: int = 400) -> dict:
     """Continuous batching of track_path requests.  Systems are drawn like the
     batch systems with n log-uniform in [8, 128]; each request picks one of
     `pool` systems, DD (p = 0.8) or QD, a random total-degree start solution
-    and gamma.  Served systems carry a planted constant term (x = 1 is a
-    root), so their paths finish: capacity from a burst of simultaneous
-    requests (paths/s), then Poisson arrivals at 0.5, 0.8 and 0.95 times that
+    and gamma.  Served systems are the finite-roots variants (per equation a
+    pure power x_i^{d_i} and a constant making x = 1 a root), so every path
+    ends at a finite root (tracked with the predictor of degree 4):
+    capacity from a burst of simultaneous requests (the completion rate
+    while the server is full: requests done by the time 80 % are done, over
+    that time; the slowest few paths, QD with n near 128, would otherwise
+    set it alone), then Poisson arrivals at 0.5, 0.8 and 0.95 times that
     capacity (p50/p99 of arrival to result, queueing and service apart), and
     the same server admitting one path at a time on the first requests of the
     0.8 trace, with their arrival times.  The literal systems (no constant
@@ -469,9 +479,9 @@ def serve_leg(hcn, S, dev, pool: int = 64, burst: int = 192, per_rate: int = 192
     import numpy as np
     lit_dd = S.batch_systems(pool, seed=5, P=2, n_range=(8, 128), log_uniform_n=True)
     lit_qd = S.batch_systems(pool, seed=5, P=4, n_range=(8, 128), log_uniform_n=True)
-    pl_dd = [S.with_root_at_ones(ps) for ps in lit_dd]
-    pl_qd = [S.with_root_at_ones(ps) for ps in lit_qd]
-    sets = {"planted": {2: pl_dd, 4: pl_qd}, "literal": {2: lit_dd, 4: lit_qd}}
+    pl_dd = [S.with_finite_roots(ps, 100 + s) for s, ps in enumerate(lit_dd)]
+    pl_qd = [S.with_finite_roots(ps, 100 + s) for s, ps in enumerate(lit_qd)]
+    sets = {"finite": {2: pl_dd, 4: pl_qd}, "literal": {2: lit_dd, 4: lit_qd}}
     loaded = {k: {P: [hcn.System(ps) for ps in v[P]] for P in (2, 4)} for k, v in sets.items()}
     max_n = max(ps.n for ps in lit_dd)
     max_slots = max(s.info().nslots for k in loaded for s in loaded[k][4])
@@ -489,8 +499,10 @@ def serve_leg(hcn, S, dev, pool: int = 64, burst: int = 192, per_rate: int = 192
         return reqs
 
     def run(kind, reqs, arrivals, serial=False, max_steps=1500):
+        order = PLANTED_ORDER if kind == "finite" else 1
         srv = hcn.Server(int(8e9), max_n=max_n, max_nslots=max_slots, qd_share=0.2,
-                         steps_per_round=8, serial=serial, max_steps=max_steps)
+                         steps_per_round=8, serial=serial, max_steps=max_steps,
+                         predictor_order=order)
         t0 = srv.now()
         last = [t0]
         nxt = 0
@@ -519,7 +531,11 @@ def serve_leg(hcn, S, dev, pool: int = 64, burst: int = 192, per_rate: int = 192
         pct = lambda a, q: 1e3 * float(np.percentile(a, q))
         codes = [int(got[i][2]["status"]) for i in range(len(reqs))]
         ok = sum(1 for c in codes if c == 0)
-        out = {"requests": len(reqs), "wall_s": wall, "paths_per_s": len(reqs) / wall,
+        done_t = np.sort(np.array([got[i][5] for i in range(len(reqs))]) - t0)
+        k80 = max(1, int(0.8 * len(reqs)))
+        out = {"requests": len(reqs), "predictor_order": order, "wall_s": wall,
+               "paths_per_s": len(reqs) / wall,
+               "paths_per_s_to_80pct": k80 / max(float(done_t[k80 - 1]), 1e-9),
                "completed_ok": ok, "completion_rate": ok / len(reqs),
                "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
                "queue_p50_ms": pct(queue, 50), "queue_p99_ms": pct(queue, 99),
@@ -527,19 +543,19 @@ def serve_leg(hcn, S, dev, pool: int = 64, burst: int = 192, per_rate: int = 192
                "status": status_hist(codes), "slots": {"dd": cap[0], "qd": cap[1]}}
         return out, got
 
-    res = {"pool_systems": pool, "systems": "planted constant term (x = 1 is a root)"}
-    progress("serving: systems loaded; planted burst")
+    res = {"pool_systems": pool, "systems": "finite-roots variants (pure powers and a constant term)"}
+    progress("serving: systems loaded; burst")
     reqs = make_requests(burst)
-    cap, _ = run("planted", reqs, np.zeros(burst))
+    cap, _ = run("finite", reqs, np.zeros(burst))
     res["capacity_burst"] = cap
     trace08 = None
     sample = []
     for lam_f in rates:
-        lam = lam_f * cap["paths_per_s"]
+        lam = lam_f * cap["paths_per_s_to_80pct"]
         rq = make_requests(per_rate)
         arr = np.cumsum(rng.exponential(1.0 / lam, size=per_rate))
         progress(f"serving: Poisson arrivals at {lam:.1f}/s ({lam_f} x capacity)")
-        r, got = run("planted", rq, arr)
+        r, got = run("finite", rq, arr)
         r["rate_per_s"] = lam
         res[f"poisson_{lam_f}"] = r
         if lam_f == 0.8:
@@ -554,7 +570,7 @@ def serve_leg(hcn, S, dev, pool: int = 64, burst: int = 192, per_rate: int = 192
                                    "status": int(got[i][2]["status"]), "steps": int(got[i][2]["steps"])})
     progress("serving: one at a time on the same trace")
     rq, arr = trace08
-    base, _ = run("planted", rq[:serial_sample], arr[:serial_sample], serial=True)
+    base, _ = run("finite", rq[:serial_sample], arr[:serial_sample], serial=True)
     res["one_at_a_time"] = base
     progress("serving: literal systems, burst")
     lit, _ = run("literal", make_requests(literal_burst), np.zeros(literal_burst),
@@ -628,6 +644,63 @@ def cyclic_leg(hcn, flops, S, dev, cases=((128, 32), (352, 4)), reps: int = 5) -
     return out
 
 
+def double_leg(hcn, flops, S, dev, B: int = 10240, reps: int = 10) -> dict:
+    """Complex double (the paper's third precision) on the dense n = 32
+    system at B points: evaluation and differentiation with the reverse
+    mode (one lane per monomial) against the tree mode (a group of lanes per
+    monomial, Section 3.2), and the whole Newton step."""
+    import torch
+    ps = S.dense32_system(0, 1)
+    pts = S.dense32_points(0, B, 1)
+    sd = hcn.System(ps)
+    x0 = torch.from_numpy(pts).to(dev)
+    out = {"points": B}
+    fm, fs = flops.eval_monomials(ps, 1), flops.eval_sums(ps, 1)
+    for mode in ("reverse", "tree"):
+        hcn.set_mon_tree(mode == "tree")
+        try:
+            hcn.eval_jac(sd, x0)
+            torch.cuda.synchronize()
+            hcn.profile_reset()
+            hcn.profile_enable(True)
+            start = torch.cuda.Event(enable_timing=True)
+            stop = torch.cuda.Event(enable_timing=True)
+            start.record()
+            for _ in range(reps):
+                hcn.eval_jac(sd, x0)
+            stop.record()
+            torch.cuda.synchronize()
+            hcn.profile_enable(False)
+            mon_ms, cnt = hcn.profile_query("eval_monomials")
+            hcn.profile_reset()
+        finally:
+            hcn.set_mon_tree(False)
+        ms = start.elapsed_time(stop) / reps
+        mon_ms /= max(cnt, 1)
+        out[mode] = {"eval_jac_ms": ms, "eval_monomials_ms": mon_ms,
+                     "monomials_tflops": fm * B / (mon_ms / 1e3) / 1e12,
+                     "eval_tflops": (fm + fs) * B / (ms / 1e3) / 1e12}
+    x = torch.empty_like(x0)
+    ws = hcn.newton_ws(sd, B)
+    x.copy_(x0)
+    hcn.newton_step(sd, x, ws=ws)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(reps):
+        x.copy_(x0)
+        hcn.newton_step(sd, x, ws=ws)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    fl = flops.newton_step(ps, 1)["total"]
+    out["newton_step"] = {"ms": ms, "steps_per_s": B / (ms / 1e3),
+                          "pct_fp64_peak": 100.0 * fl * B / (ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS}
+    sd.free()
+    return out
+
+
 def run_gpu(steps: int, warmup: int, qd_steps: int, legs, sparse_variants=None) -> dict:
     import torch
     from paper_1501_06625_amd import flops, hcn, systems as S
@@ -644,21 +717,34 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs, sparse_variants=None) 
     if "single" in legs:
         progress("single-path leg")
         out["single"] = dense_leg(hcn, flops, S, dev, 2, 1, 200, 5, profile=False, keep=1)
+    def show(key):
+        leg = {k: v for k, v in out[key].items() if k != "sample"}
+        progress(f"{key}: " + json.dumps(leg, default=str)[:3000])
+
     if "track8" in legs:
         progress("single-path tracking leg (n = 8)")
         out["track8"] = track8_leg(hcn, S, dev)
+        show("track8")
     if "sparse512" in legs:
         progress("sparse n=512 leg")
         out["sparse512"] = sparse512_leg(hcn, flops, S, dev, variants=sparse_variants)
+        show("sparse512")
     if "batch64" in legs:
         progress("64-system batch leg")
         out["batch64"] = batch_leg(hcn, flops, S, dev)
-    if "serve" in legs:
-        progress("serving leg")
-        out["serve"] = serve_leg(hcn, S, dev)
+        show("batch64")
     if "cyclic" in legs:
         progress("cyclic n-roots leg")
         out["cyclic"] = cyclic_leg(hcn, flops, S, dev)
+        show("cyclic")
+    if "double" in legs:
+        progress("complex double leg")
+        out["double"] = double_leg(hcn, flops, S, dev)
+        show("double")
+    if "serve" in legs:
+        progress("serving leg")
+        out["serve"] = serve_leg(hcn, S, dev)
+        show("serve")
     progress("GPU legs done")
     return out
 
@@ -823,6 +909,28 @@ def track_errors(O, items, threads: int) -> dict:
             "oracle_threads": threads}
 
 
+def endpoint_errors(O, items, threads: int) -> dict:
+    """End points of tracked paths too long for the oracle to track again
+    (n up to 128, hundreds of steps): for each end point that the GPU reports
+    converged, the oracle's quad-double residual there and the size of one
+    oracle Newton step in quad-double from it (its distance to the root the
+    path reached, to first order)."""
+    def one(it):
+        if it["status"] != 0:
+            return None
+        ps4 = _widen(it["ps"], 4)
+        x4 = _to_p(it["x1"], 4)
+        f4, _ = O.eval_jac(ps4, x4)
+        rc, xn, nr = O.newton_step(ps4, None, None, 1, 1.0, x4)
+        return lead_abs_max(f4), (float(nr[1]) if rc == 0 else float("inf"))
+
+    with cf.ThreadPoolExecutor(max(1, threads)) as ex:
+        rs = [r for r in ex.map(one, items) if r is not None]
+    return {"paths": len(items), "converged_checked": len(rs),
+            "max_qd_residual": max((r[0] for r in rs), default=None),
+            "max_qd_newton_step": max((r[1] for r in rs), default=None)}
+
+
 def time_newton_steps(O, ps, pts, threads: int, target_s: float) -> dict:
     """The oracle's Newton step on distinct points, one thread per core (the
     oracle is C called through ctypes, which releases the GIL)."""
@@ -886,16 +994,15 @@ def cpu_baseline(gpu: dict, target_s: float = 15.0):
         ps = S.sparse512_system(0, 2)
         errs["sparse512"] = sparse_errors(O, ps, smp["x0"], smp["x1"])
     if gpu.get("batch64"):
-        progress("oracle errors: planted batch paths")
+        progress("oracle errors: batch paths")
         smp = gpu["batch64"]["sample"]
-        items = [dict(p, ps=smp["systems"][p["system"]], gamma=smp["gammas"][p["system"]])
-                 for p in smp["paths"]]
-        errs["batch64"] = track_errors(O, items, threads)
+        items = [dict(p, ps=smp["systems"][p["system"]]) for p in smp["paths"]]
+        errs["batch64"] = endpoint_errors(O, items, threads)
     if gpu.get("serve"):
         progress("oracle errors: served paths")
         smp = gpu["serve"]["sample"]
         items = [dict(p, ps=smp["systems"][p["P"]][p["system"]]) for p in smp["paths"]]
-        errs["serve"] = track_errors(O, items, threads)
+        errs["serve"] = endpoint_errors(O, items, threads)
     progress("CPU leg done")
     return base, errs
 
@@ -911,9 +1018,9 @@ def main() -> int:
                     help="pin the MGS lane-group width (8/16/32) instead of autotuning")
     ap.add_argument("--mgs-storage", type=int, default=0,
                     help="with --mgs-group: [A | b] in global memory (0), LDS (1) or registers (2)")
-    ap.add_argument("--legs", default="dd,qd,single,track8,sparse512,batch64,serve,cyclic",
+    ap.add_argument("--legs", default="dd,qd,single,track8,sparse512,batch64,serve,cyclic,double",
                     help="comma list of dd (the reported line), qd, single, track8, sparse512, "
-                         "batch64, serve, cyclic")
+                         "batch64, serve, cyclic, double")
     ap.add_argument("--sparse512-variants", default=None,
                     help="comma list of MGS variants for the sparse512 leg (" +
                          ", ".join(r[2] for r in SPARSE_RUNS) + "); default all")
@@ -1023,6 +1130,7 @@ def main() -> int:
         "batch64": with_err(r.get("batch64"), "batch64"),
         "serve": with_err(r.get("serve"), "serve"),
         "cyclic": strip(r.get("cyclic")),
+        "double": strip(r.get("double")),
     }
     if rank == 0:
         print(json.dumps(line), flush=True)

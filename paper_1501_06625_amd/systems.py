@@ -321,6 +321,40 @@ def with_root_at_ones(sys: PolySystem) -> PolySystem:
                                  name=sys.name + "+root1")
 
 
+def with_finite_roots(sys: PolySystem, seed: int = 0) -> PolySystem:
+    """Append to every equation i a pure power c_i x_i^{d_i} (d_i the
+    equation's degree, c_i = exp(i theta), theta ~ U[0, 2 pi) seeded), then
+    the constant term minus the sum of all its coefficients, so that
+    x = (1, ..., 1) is a root (the sum formed at 320 bits).  The pure powers
+    put x_i^{d_i} in the leading form of equation i, so (for random
+    coefficients) the leading forms have no common zero: the system has no
+    roots at infinity and every path of the total-degree homotopy ends at a
+    finite root.  The literal random systems have no constant term and
+    far fewer finite roots than the total degree, so most of their paths
+    diverge."""
+    P = sys.P
+    rng = rng_for(8, seed)
+    degs = degrees(sys)
+    eqs, coefs = [], []
+    for i in range(sys.N):
+        mons = []
+        with mpmath.workprec(_MP_PREC):
+            acc = mpmath.mpc(0)
+            for m, mon in sys.monomials(i):
+                mons.append(mon)
+                coefs.append(np.asarray(sys.coef[m]))
+                acc += limbs_to_complex(sys.coef[m])
+            c = unit_complex(np.array([rng.uniform(0.0, 2.0 * math.pi)]), P)[0]
+            mons.append([(i, int(degs[i]))])
+            coefs.append(c)
+            acc += limbs_to_complex(c)
+            mons.append([])
+            coefs.append(complex_to_limbs(-acc, P))
+        eqs.append(mons)
+    return system_from_monomials(sys.N, sys.n, P, eqs, np.asarray(coefs),
+                                 name=sys.name + "+finite")
+
+
 def diagonal_power_system(cs: np.ndarray, d: int, P: int) -> PolySystem:
     """f_i = x_i^d - c_i, i = 0..n-1 (coefficient of x_i^d is 1); cs: [n][2][P]."""
     n = cs.shape[0]

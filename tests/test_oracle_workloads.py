@@ -145,3 +145,28 @@ def test_double_newton_converges_to_planted_root():
         assert rc == 0
     err = np.abs((x[:, 0, 0] - root[:, 0, 0]) + 1j * (x[:, 1, 0] - root[:, 1, 0])).max()
     assert err <= 1e-13
+
+
+def test_finite_roots_variant():
+    """The finite-roots variant of a random system: x = 1 is a root (the
+    oracle's residual there is at rounding level), every equation holds the
+    pure power of its own variable at its degree, and total-degree paths of
+    a small such system end at finite, refined roots (the literal system's
+    end at the step limit or shrink below the smallest step)."""
+    P = 2
+    base = S.batch_systems(1, seed=11, P=P, n_range=(10, 10))[0]
+    fin = S.with_finite_roots(base, 3)
+    degs = S.degrees(base)
+    assert np.array_equal(S.degrees(fin), degs)
+    for i in range(fin.N):
+        mons = [m for _, m in fin.monomials(i)]
+        assert [(i, int(degs[i]))] in mons and [] in mons
+    f, _ = O.eval_jac(fin, S.ones_point(fin.n, P))
+    assert np.abs(f[:, :, 0]).max() <= 100 * TOL[P]
+    rng = S.rng_for(9, 77)
+    gam = S.random_unit_gamma(rng, P)
+    g = O.total_degree_start(fin)
+    for _ in range(2):
+        x0 = S.start_solution(rng, degs, P)
+        _, r = O.track(fin, g, gam, 1, x0, predictor_order=4)
+        assert r.status == O.OK and r.end_status == O.OK and r.steps < 1500
