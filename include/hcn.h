@@ -73,7 +73,7 @@ typedef struct hcn_sys_s *hcn_sys;
  *   eq_ptr  [N+1]   equations as a CSR over monomials (eq_ptr[0] = 0),
  *   mon_ptr [nmon+1] monomials as a CSR over (variable, exponent) pairs,
  *   var, exp [npairs] variable index in 0..n-1, distinct within a
- *           monomial, exponent 1..15; a monomial with no pair is a
+ *           monomial, exponent 1..255; a monomial with no pair is a
  *           constant term,
  *   coef    [nmon][2][P] complex coefficients.
  * Requires P in {1, 2, 4} and 1 <= n <= N <= 4096 (a monomial has at most n

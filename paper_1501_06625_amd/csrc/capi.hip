@@ -211,8 +211,8 @@ int hcn_sys_load(hcn_sys *out, int N, int n, int P, const int32_t *eq_ptr, const
             for (int q = mon_ptr[m]; q < mon_ptr[m + 1]; ++q) {
                 if (var[q] < 0 || var[q] >= n)
                     return fail(HCN_EINVAL, "hcn_sys_load: variable %d out of range", var[q]);
-                if (exp[q] < 1 || exp[q] > 15)
-                    return fail(HCN_EINVAL, "hcn_sys_load: exponent %d out of 1..15", exp[q]);
+                if (exp[q] < 1 || exp[q] > 255)
+                    return fail(HCN_EINVAL, "hcn_sys_load: exponent %d out of 1..255", exp[q]);
                 if (seen[var[q]] == m)
                     return fail(HCN_EINVAL, "hcn_sys_load: variable %d repeated in monomial %d",
                                 var[q], m);

@@ -18,7 +18,7 @@
 // columns (column j belongs to workgroup j mod G and stays in its LDS for
 // the whole factorisation).  The owner of column k normalises it and
 // publishes q_k in place in A (the column's final value) with a flag;
-// every workgroup waits for the flags in order, stages q_k in LDS and
+// every workgroup waits for the flags in order, reads q_k from A and
 // projects it out of its own later columns, the next column first, so that
 // the owner of column k+1 can publish q_{k+1} while the others still work
 // on q_k (look-ahead).  The column operations are the right-looking
@@ -49,21 +49,14 @@ namespace hcn {
 
 constexpr int BT = MGS_THREADS;
 
-HCN_DEV double bshfl(double v, int m) { return __shfl_xor(v, m); }
-HCN_DEV dd bshfl(const dd &v, int m) { return dd{bshfl(v.hi, m), bshfl(v.lo, m)}; }
-HCN_DEV qd bshfl(const qd &v, int m) {
-    return qd{bshfl(v.c0, m), bshfl(v.c1, m), bshfl(v.c2, m), bshfl(v.c3, m)};
-}
-
-// full workgroup sums; every lane returns the same bits
+// full workgroup sums: a 64-lane butterfly adding the lower lane first
+// (group_csum / group_sum: DPP moves within rows of 16 lanes, permutes
+// beyond), then the four wavefront sums in order; every lane returns the
+// same bits
 template <class R>
 HCN_DEV cx<R> wg_csum(cx<R> v, cx<R> *s_part) {
     const int tid = threadIdx.x, lane = tid & 63;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const cx<R> o{bshfl(v.re, m), bshfl(v.im, m)};
-        v = (lane & m) ? cadd(o, v) : cadd(v, o);
-    }
+    v = group_csum<R, 64>(v, lane);
     if (lane == 0) s_part[tid >> 6] = v;
     __syncthreads();
     cx<R> s = s_part[0];
@@ -76,11 +69,7 @@ HCN_DEV cx<R> wg_csum(cx<R> v, cx<R> *s_part) {
 template <class R>
 HCN_DEV R wg_rsum(R v, R *s_part) {
     const int tid = threadIdx.x, lane = tid & 63;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-        const R o = bshfl(v, m);
-        v = (lane & m) ? add(o, v) : add(v, o);
-    }
+    v = group_sum<R, 64>(v, lane);
     if (lane == 0) s_part[tid >> 6] = v;
     __syncthreads();
     R s = s_part[0];
@@ -135,28 +124,23 @@ HCN_DEV void col_scale(double *a, const R &iv, int N) {
 }
 
 // r_jj = ||a_j||, 1/r_jj and q_j = a_j / r_jj on the column at `aj`; writes
-// R[j][j] and inv[j].  Returns false (on every lane) for a singular column.
+// R[j][j] and inv[j].  Every lane holds the same squared norm, so every lane
+// forms r_jj and 1/r_jj itself (the same bits; no broadcast).  Returns false
+// (on every lane) for a singular column.
 template <class R>
-HCN_DEV bool col_normalise(const MgsArgs &a, int b, int j, double *aj, R *s_part, R *s_inv,
-                           int *s_bad) {
+HCN_DEV bool col_normalise(const MgsArgs &a, int b, int j, double *aj, R *s_part) {
     constexpr int P = limbs<R>::P;
     constexpr int W = 2 * P;
     const R s = col_norm2<R>(aj, a.N, s_part);
+    const R rkk = sqrt(s);
+    if (!(lead(rkk) > 0.0) || !rfinite(rkk)) return false;
+    const R iv = div(rmake<R>(1.0), rkk);
     if (threadIdx.x == 0) {
-        const R rkk = sqrt(s);
-        const bool bad = !(lead(rkk) > 0.0) || !rfinite(rkk);
-        *s_bad = bad ? 1 : 0;
-        if (!bad) {
-            const R iv = div(rmake<R>(1.0), rkk);
-            *s_inv = iv;
-            rstore(a.inv + (size_t)b * a.inv_pstride + (size_t)j * P, iv);
-            const cx<R> rc{rkk, rmake<R>(0.0)};
-            cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * a.n + j) * W, rc);
-        }
+        rstore(a.inv + (size_t)b * a.inv_pstride + (size_t)j * P, iv);
+        const cx<R> rc{rkk, rmake<R>(0.0)};
+        cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * a.n + j) * W, rc);
     }
-    __syncthreads();
-    if (*s_bad) return false;
-    col_scale<R>(aj, *s_inv, a.N);
+    col_scale<R>(aj, iv, a.N);
     return true;
 }
 
@@ -178,8 +162,6 @@ __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
     constexpr int W = 2 * limbs<R>::P;
     __shared__ cx<R> s_part[BT / 64];
     __shared__ R s_rpart[BT / 64];
-    __shared__ R s_inv;
-    __shared__ int s_bad;
     const int b = blockIdx.y;
     if (!problem_live(a, b) || sing[b]) return;
     const int j = (k < 0) ? 0 : k + 1 + (int)blockIdx.x;
@@ -193,7 +175,7 @@ __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
         col_axpy<R>(qk, aj, r, a.N);
     }
     if (j == k + 1 && j < a.n) {
-        if (!col_normalise<R>(a, b, j, aj, s_rpart, &s_inv, &s_bad) && threadIdx.x == 0) sing[b] = 1;
+        if (!col_normalise<R>(a, b, j, aj, s_rpart) && threadIdx.x == 0) sing[b] = 1;
     }
 }
 
@@ -233,18 +215,16 @@ template <class R>
 __global__ __launch_bounds__(BT) void k_mgs_pipe(MgsArgs a, int *sing, int *flags, long spin_limit) {
     constexpr int P = limbs<R>::P;
     constexpr int W = 2 * P;
-    extern __shared__ double lds[];  // own columns [c][N][W], then q_k [N][W]
+    extern __shared__ double lds[];  // own columns [c][N][W]
     __shared__ cx<R> s_part[BT / 64];
     __shared__ R s_rpart[BT / 64];
-    __shared__ R s_inv;
-    __shared__ int s_bad, s_go;
+    __shared__ int s_go;
     const int b = blockIdx.y;
     if (!problem_live(a, b)) return;
     const int G = gridDim.x, w = blockIdx.x, n = a.n, N = a.N;
     const size_t cst = (size_t)N * W;
     if (w > n) return;
     const int mine = (n - w) / G + 1;  // columns w, w + G, ...
-    double *q = lds + (size_t)mine * cst;
     int *flg = flags + (size_t)b * (n + 1);
     int *stop = sing + b;
     for (int c = 0; c < mine; ++c) {
@@ -257,7 +237,7 @@ __global__ __launch_bounds__(BT) void k_mgs_pipe(MgsArgs a, int *sing, int *flag
     auto publish = [&](int c) -> bool {
         const int j = w + c * G;
         double *aj = lds + (size_t)c * cst;
-        if (!col_normalise<R>(a, b, j, aj, s_rpart, &s_inv, &s_bad)) {
+        if (!col_normalise<R>(a, b, j, aj, s_rpart)) {
             if (threadIdx.x == 0)
                 __hip_atomic_store(stop, PIPE_SINGULAR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
@@ -284,10 +264,9 @@ __global__ __launch_bounds__(BT) void k_mgs_pipe(MgsArgs a, int *sing, int *flag
                 live = false;
                 break;
             }
-            const double *src = col_ptr(a, b, k);
-            for (size_t t = threadIdx.x; t < cst; t += BT) q[t] = src[t];
-            __syncthreads();
-            qk = q;
+            // each lane reads its own rows of the published q_k (the first
+            // column's dot product fetches them, later ones hit the caches)
+            qk = col_ptr(a, b, k);
         }
         // own columns j > k in increasing order (column k+1 first)
         const int c0 = k < w ? 0 : (k - w) / G + 1;
@@ -300,7 +279,6 @@ __global__ __launch_bounds__(BT) void k_mgs_pipe(MgsArgs a, int *sing, int *flag
             col_axpy<R>(qk, aj, r, N);
             if (j == k + 1 && j < n) live = publish(c);
         }
-        __syncthreads();  // q is staged again for the next k
     }
     // the projected right-hand side (column n) goes back to its place
     if (live && n % G == w) {
@@ -423,7 +401,7 @@ static int pipe_groups(const MgsArgs &a, size_t *lds_out) {
     int G = std::min(cus / std::max(a.B, 1), a.n + 1);
     if (G < 1) return 0;
     const int mine = a.n / G + 1;
-    const size_t lds = (size_t)(mine + 1) * cst;
+    const size_t lds = (size_t)mine * cst;
     if (lds > 160 * 1024) return 0;
     (void)hipFuncSetAttribute((const void *)k_mgs_pipe<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)lds);

@@ -1,5 +1,6 @@
 """GPU parity for inputs beyond the basic workloads, all through the C ABI:
-exponents up to 15, the relaxation exponent k >= 2 of equation (1),
+exponents up to 15 and, as pure powers, up to 36, the relaxation exponent
+k >= 2 of equation (1),
 extrapolation of degree 2..4 (Section 3.1), QD tracking of random systems,
 overdetermined Newton (N > n, least squares through the same MGS), a
 system of the shape of the 64-system batch (n = 96, 64 monomials of 12
@@ -88,6 +89,44 @@ def test_eval_high_exponents(H, P, n, uniform):
         _check_eval(H, ps, xs)
     finally:
         H.set_mon_uniform(True)
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_eval_finite_roots_variant(H, P):
+    """The finite-roots variant of a batch-shaped system (per equation the
+    pure power x_i^{d_i}, d_i up to 36, and a constant term): exponents far
+    beyond the power table (the branching form takes them), against the
+    oracle at points near the unit circle and at the root x = 1."""
+    base = S.batch_systems(1, seed=21, P=P, n_range=(20, 20))[0]
+    ps = S.with_finite_roots(base, 5)
+    assert ps.exp.max() > 15
+    rng = S.rng_for(7, 300 + P)
+    xs = np.concatenate([_points_near_unit(rng, 2, ps.n, P), S.ones_point(ps.n, P)[None]])
+    _check_eval(H, ps, xs)
+
+
+def test_track_finite_roots_parity(H):
+    """Two paths of a finite-roots system (n = 10) tracked with the degree-4
+    predictor: the oracle's decisions and step counts, converged endpoints
+    within the bound."""
+    P = 2
+    base = S.batch_systems(1, seed=11, P=P, n_range=(10, 10))[0]
+    ps = S.with_finite_roots(base, 3)
+    g = O.total_degree_start(ps)
+    rng = S.rng_for(9, 77)
+    gam = S.random_unit_gamma(rng, P)
+    sysd = H.System(ps)
+    degs = S.degrees(ps)
+    for _ in range(2):
+        x0 = S.start_solution(rng, degs, P)
+        xg, res = H.track_paths(sysd, gam, dev(x0[None]), predictor_order=4)
+        xg, res = host(xg)[0], res[0]
+        xo, r = O.track(ps, g, gam, 1, x0, predictor_order=4)
+        assert r.status == O.OK and r.end_status == O.OK
+        assert (res["status"], res["steps"], res["accepted"], res["newton_iters"]) == \
+            (r.status, r.steps, r.accepted, r.newton_iters)
+        assert (res["end_status"], res["end_iters"]) == (r.end_status, r.end_iters)
+        _endpoint_close(ps, xg, xo, res["res_norm"], r.res_norm, P)
 
 
 # ---------------------------------------------------------------------------
