@@ -60,15 +60,21 @@ HBM_PEAK_GBS = 8000.0
 # MGS per lane-group width and storage of [A | b], from the autotuner's
 # launches), calibrated on the 10 MiB copy of the start points in the same
 # runs (FETCH_SIZE reads 5131.5 KiB, WRITE_SIZE 10240 KiB for 10,485,760
-# bytes).  The figures hold for the kernel sources whose digest is
-# COUNTERS_DIGEST (source_digest()); other sources report traffic null.
+# bytes).  The figures of a kernel hold for the sources whose digest is
+# COUNTERS_DIGEST[kernel] (source_digest(kernel), over KERNEL_SOURCES[kernel]);
+# other sources report traffic null.
 HBM_COUNTERS_KIB = {
     "mgs": {(8, 0): (914308.5, 5363301.7), (8, 1): (274850.0, 205529.5), (8, 2): (274997.6, 206119.3),
             (8, 3): (437086.8, 542545.7), (16, 0): (876101.0, 4627639.1), (16, 1): (274880.8, 205993.9),
             (16, 2): (275024.4, 205809.6), (16, 3): (451486.8, 540727.1), (32, 0): (793216.0, 3988355.4),
             (32, 1): (274887.6, 207304.7), (32, 3): (479989.7, 537147.9)},
     "eval_monomials": (38055.1, 5570560.0), "eval_sums": (3648677.0, 393871.9)}
-COUNTERS_DIGEST = None  # taken before the digest existed: retaken before they are reported again
+KERNEL_SOURCES = {
+    "mgs": ("mgs.hip", "mgs_common.hpp", "mp.hpp", "internal.hpp", "tune.hip"),
+    "eval_monomials": ("eval.hip", "eval_body.hpp", "mp.hpp", "internal.hpp"),
+    "eval_sums": ("eval.hip", "eval_body.hpp", "mp.hpp", "internal.hpp"),
+}
+COUNTERS_DIGEST = {}
 MGS_PIN = None  # (lane group, storage) from --mgs-group / --mgs-storage, else autotuned
 FETCH_CAL, WRITE_CAL = 10485760 / (5131.5 * 1024), 1.0
 _T0 = time.time()
@@ -81,15 +87,15 @@ def progress(msg: str) -> None:
     print(f"[bench {time.time() - _T0:7.1f}s] {msg}", file=sys.stderr, flush=True)
 
 
-def source_digest() -> str:
-    """Digest of the kernel sources (the counter figures hold for one)."""
+def source_digest(kernel: str) -> str:
+    """Digest of the sources a kernel is built from (its counter figures
+    hold for one digest)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1501_06625_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".hpp")):
-            h.update(f.encode())
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES.get(kernel, ()):
+        h.update(f.encode())
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -290,11 +296,45 @@ def sparse512_leg(hcn, flops, S, dev, reps: int = 10, variants=None) -> dict:
                                                                             ref.view(np.uint64)))
     res["mgs_gflop"] = mgs_flops / 1e9
     res["sample"] = {"x0": pts[0], "x1": outs}
+    # two points of the system at once (paths of one system tracked
+    # together): the two pipelined chains share the CUs (two workgroups per
+    # CU; more would not fit the LDS with n = 512)
+    if not variants or "pipelined" in variants:
+        for B in (2,):
+            ptsB = S.random_unit_point(S.rng_for(2, 100 + B), ps.n * B, 2).reshape(B, ps.n, 2, 2)
+            sysd = hcn.System(ps)
+            xB0 = torch.from_numpy(ptsB).to(dev)
+            xB = torch.empty_like(xB0)
+            wsB = hcn.newton_ws(sysd, B)
+            hcn.set_mgs_variant(5)
+            xB.copy_(xB0)
+            hcn.newton_step(sysd, xB, ws=wsB)
+            torch.cuda.synchronize()
+            hcn.profile_reset()
+            hcn.profile_enable(True)
+            start = torch.cuda.Event(enable_timing=True)
+            stop = torch.cuda.Event(enable_timing=True)
+            start.record()
+            for _ in range(reps):
+                xB.copy_(xB0)
+                hcn.newton_step(sysd, xB, ws=wsB)
+            stop.record()
+            torch.cuda.synchronize()
+            hcn.profile_enable(False)
+            ms_mgs, cnt = hcn.profile_query("mgs")
+            hcn.profile_reset()
+            hcn.set_mgs_variant(0)
+            mgs_ms = ms_mgs / max(cnt, 1)
+            res[f"pipelined_{B}_points"] = {
+                "newton_step_ms": start.elapsed_time(stop) / reps, "mgs_ms": mgs_ms,
+                "mgs_tflops": B * mgs_flops / (mgs_ms / 1e3) / 1e12,
+                "mgs_frac_fp64_peak": B * mgs_flops / (mgs_ms / 1e3) / 1e12 / FP64_PEAK_TFLOPS}
+            sysd.free()
     return res
 
 
 def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10,
-              split_n: int = 0) -> dict:
+              split_n: int = 0, steps_only: bool = False) -> dict:
     """64 random systems (n in [16, 96], 16..64 monomials per equation, 4..12
     variables per monomial, exponents 1..3), 64 total-degree start solutions
     each: 4096 paths in one slot-table batch, in complex DD.
@@ -380,6 +420,8 @@ def batch_leg(hcn, flops, S, dev, nsys: int = 64, per: int = 64, steps: int = 10
         bt.free()
     for s in loaded:
         s.free()
+    if steps_only:
+        return res
 
     # finite-roots variant: paths to completion, and Newton to 1e-28
     progress("batch: finite-roots systems")
@@ -701,7 +743,8 @@ def double_leg(hcn, flops, S, dev, B: int = 10240, reps: int = 10) -> dict:
     return out
 
 
-def run_gpu(steps: int, warmup: int, qd_steps: int, legs, sparse_variants=None) -> dict:
+def run_gpu(steps: int, warmup: int, qd_steps: int, legs, sparse_variants=None,
+            batch_steps_only: bool = False) -> dict:
     import torch
     from paper_1501_06625_amd import flops, hcn, systems as S
 
@@ -731,7 +774,7 @@ def run_gpu(steps: int, warmup: int, qd_steps: int, legs, sparse_variants=None) 
         show("sparse512")
     if "batch64" in legs:
         progress("64-system batch leg")
-        out["batch64"] = batch_leg(hcn, flops, S, dev)
+        out["batch64"] = batch_leg(hcn, flops, S, dev, steps_only=batch_steps_only)
         show("batch64")
     if "cyclic" in legs:
         progress("cyclic n-roots leg")
@@ -993,7 +1036,7 @@ def cpu_baseline(gpu: dict, target_s: float = 15.0):
         smp = gpu["sparse512"]["sample"]
         ps = S.sparse512_system(0, 2)
         errs["sparse512"] = sparse_errors(O, ps, smp["x0"], smp["x1"])
-    if gpu.get("batch64"):
+    if gpu.get("batch64") and "sample" in gpu["batch64"]:
         progress("oracle errors: batch paths")
         smp = gpu["batch64"]["sample"]
         items = [dict(p, ps=smp["systems"][p["system"]]) for p in smp["paths"]]
@@ -1024,6 +1067,8 @@ def main() -> int:
     ap.add_argument("--sparse512-variants", default=None,
                     help="comma list of MGS variants for the sparse512 leg (" +
                          ", ".join(r[2] for r in SPARSE_RUNS) + "); default all")
+    ap.add_argument("--batch-steps-only", action="store_true",
+                    help="batch64: only the fixed-step timing (no paths to completion; for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported "
@@ -1038,7 +1083,7 @@ def main() -> int:
     if "dd" not in legs:
         legs = ("dd",) + legs
     sv = tuple(args.sparse512_variants.split(",")) if args.sparse512_variants else None
-    r = run_gpu(args.steps, args.warmup, args.qd_steps, legs, sv)
+    r = run_gpu(args.steps, args.warmup, args.qd_steps, legs, sv, args.batch_steps_only)
     cpu, errs = (None, {})
     if rank == 0 and not args.no_cpu:
         cpu, errs = cpu_baseline(r)
@@ -1054,8 +1099,8 @@ def main() -> int:
     achieved = flops_launch / (avg_ms / 1e3) / 1e12
     traffic = None
     tuned_cfg = tuple(dd["tuned"][:2]) if dd["tuned"] else (16, 0)
-    digest = source_digest()
-    counters = HBM_COUNTERS_KIB.get(dom) if digest == COUNTERS_DIGEST else None
+    digest = source_digest(dom)
+    counters = HBM_COUNTERS_KIB.get(dom) if digest == COUNTERS_DIGEST.get(dom) else None
     if isinstance(counters, dict):
         counters = counters.get(tuned_cfg)
     if counters is not None and dd["B"] == B_DD:

@@ -144,7 +144,7 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A_dev, double *b_dev,
                   void *ws_dev, size_t ws_bytes, void *stream);
 
 /* Select the MGS variant used by every solve (process-wide): 0 automatic
- * (2 for large single problems, else 1), 1 one workgroup per problem,
+ * (5 for large single problems, else 1), 1 one workgroup per problem,
  * 2 right-looking across workgroups (one launch per column step, the
  * trailing matrix re-read every step), 4 tiled (Section 1: right-looking
  * over panels of T columns, each panel factored by one workgroup with its

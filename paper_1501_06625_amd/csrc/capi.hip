@@ -87,7 +87,7 @@ size_t g_chunk_bytes = 0;  // 0: every launch covers the whole batch
 // the MGS variant for B problems with n unknowns
 int mgs_variant_for(int n, int B) {
     if (g_mgs_variant != 0) return g_mgs_variant;
-    return (n >= 160 && B <= 4) ? 2 : 1;
+    return (n >= 160 && B <= 4) ? 5 : 1;
 }
 
 int enqueue_mgs_variant(int P, const MgsArgs &a, int variant, int *ints, hipStream_t s) {

@@ -16,8 +16,9 @@
 //
 // Pipelined (one cooperative launch): a persistent workgroup per slice of
 // columns (column j belongs to workgroup j mod G and stays in its LDS for
-// the whole factorisation).  The owner of column k normalises it and
-// publishes q_k in place in A (the column's final value) with a flag;
+// the whole factorisation; one workgroup per CU, so the chain of column
+// steps always has a CU of its own).  The owner of column k normalises it
+// and publishes q_k in place in A (the column's final value) with a flag;
 // every workgroup waits for the flags in order, reads q_k from A and
 // projects it out of its own later columns, the next column first, so that
 // the owner of column k+1 can publish q_{k+1} while the others still work
@@ -49,98 +50,166 @@ namespace hcn {
 
 constexpr int BT = MGS_THREADS;
 
-// full workgroup sums: a 64-lane butterfly adding the lower lane first
+// Team operations on one column.  A team is 256 lanes (four wavefronts);
+// lane t of the team holds rows t, t + 256, ... .  A sum over the column is
+// lane t's rows in order, a 64-lane butterfly adding the lower lane first
 // (group_csum / group_sum: DPP moves within rows of 16 lanes, permutes
-// beyond), then the four wavefront sums in order; every lane returns the
-// same bits
+// beyond), then the four wavefront sums in order, so every lane of the team
+// returns the same bits.  The right-looking workgroup is one team; the
+// pipelined workgroup is one team too.  `act` false: the lane adds no rows
+// (its part of the sum is zero) but keeps the barriers.
+constexpr int TEAM = MGS_THREADS;
+
 template <class R>
-HCN_DEV cx<R> wg_csum(cx<R> v, cx<R> *s_part) {
-    const int tid = threadIdx.x, lane = tid & 63;
+HCN_DEV cx<R> team_csum(cx<R> v, int t, cx<R> *s_part) {
+    const int lane = t & 63;
     v = group_csum<R, 64>(v, lane);
-    if (lane == 0) s_part[tid >> 6] = v;
+    if (lane == 0) s_part[t >> 6] = v;
     __syncthreads();
     cx<R> s = s_part[0];
 #pragma unroll
-    for (int w = 1; w < BT / 64; ++w) s = cadd(s, s_part[w]);
+    for (int w = 1; w < TEAM / 64; ++w) s = cadd(s, s_part[w]);
     __syncthreads();
     return s;
 }
 
 template <class R>
-HCN_DEV R wg_rsum(R v, R *s_part) {
-    const int tid = threadIdx.x, lane = tid & 63;
+HCN_DEV R team_rsum(R v, int t, R *s_part) {
+    const int lane = t & 63;
     v = group_sum<R, 64>(v, lane);
-    if (lane == 0) s_part[tid >> 6] = v;
+    if (lane == 0) s_part[t >> 6] = v;
     __syncthreads();
     R s = s_part[0];
 #pragma unroll
-    for (int w = 1; w < BT / 64; ++w) s = add(s, s_part[w]);
+    for (int w = 1; w < TEAM / 64; ++w) s = add(s, s_part[w]);
     __syncthreads();
     return s;
 }
 
+// A column as rows of complex numbers: limb l of row i at p[i * step + l * ld].
+// In global memory a column is interleaved (step = 2P, ld = 1, the
+// boundary's layout); the pipelined variant keeps its columns planar in
+// LDS (step = 1, ld = N: limb planes of N doubles), so that the 64 lanes of
+// a wavefront reading one limb of consecutive rows touch consecutive
+// doubles instead of doubles 2P apart (bank conflicts).
+struct Col {
+    double *p;
+    int ld, step;
+};
 template <class R>
-HCN_DEV cx<R> col_dot(const double *q, const double *a, int N, cx<R> *s_part) {
+HCN_DEV Col interleaved(double *p) {
+    return Col{p, 1, 2 * limbs<R>::P};
+}
+HCN_DEV Col planar(double *p, int N) { return Col{p, N, 1}; }
+
+template <class R>
+HCN_DEV cx<R> col_ld(const Col &c, int i) {
     constexpr int W = 2 * limbs<R>::P;
+    double v[W];
+#pragma unroll
+    for (int l = 0; l < W; ++l) v[l] = c.p[(size_t)i * c.step + (size_t)l * c.ld];
+    return cload<R>(v);
+}
+template <class R>
+HCN_DEV void col_st(const Col &c, int i, const cx<R> &x) {
+    constexpr int W = 2 * limbs<R>::P;
+    double v[W];
+    cstore(v, x);
+#pragma unroll
+    for (int l = 0; l < W; ++l) c.p[(size_t)i * c.step + (size_t)l * c.ld] = v[l];
+}
+
+// q^H a over the column
+template <class R>
+HCN_DEV cx<R> col_dot(const Col &q, const Col &a, int N, int t, cx<R> *s_part, bool act = true) {
     cx<R> acc = czero<R>();
     bool first = true;
-    for (int i = threadIdx.x; i < N; i += BT) {
-        const cx<R> v = cmul_conj(cload<R>(q + (size_t)i * W), cload<R>(a + (size_t)i * W));
-        acc = first ? v : cadd(acc, v);
-        first = false;
+    if (act) {
+        for (int i = t; i < N; i += TEAM) {
+            const cx<R> v = cmul_conj(col_ld<R>(q, i), col_ld<R>(a, i));
+            acc = first ? v : cadd(acc, v);
+            first = false;
+        }
     }
-    return wg_csum(acc, s_part);
+    return team_csum(acc, t, s_part);
 }
 
 template <class R>
-HCN_DEV void col_axpy(const double *q, double *a, const cx<R> &r, int N) {
-    constexpr int W = 2 * limbs<R>::P;
-    for (int i = threadIdx.x; i < N; i += BT) {
-        double *p = a + (size_t)i * W;
-        cstore(p, csub(cload<R>(p), cmul(r, cload<R>(q + (size_t)i * W))));
-    }
+HCN_DEV void col_axpy(const Col &q, const Col &a, const cx<R> &r, int N, int t) {
+    for (int i = t; i < N; i += TEAM) col_st<R>(a, i, csub(col_ld<R>(a, i), cmul(r, col_ld<R>(q, i))));
 }
 
 template <class R>
-HCN_DEV R col_norm2(const double *a, int N, R *s_part) {
-    constexpr int W = 2 * limbs<R>::P;
+HCN_DEV R col_norm2(const Col &a, int N, int t, R *s_part, bool act = true) {
     R acc = rmake<R>(0.0);
     bool first = true;
-    for (int i = threadIdx.x; i < N; i += BT) {
-        const R v = cnorm2(cload<R>(a + (size_t)i * W));
-        acc = first ? v : add(acc, v);
-        first = false;
+    if (act) {
+        for (int i = t; i < N; i += TEAM) {
+            const R v = cnorm2(col_ld<R>(a, i));
+            acc = first ? v : add(acc, v);
+            first = false;
+        }
     }
-    return wg_rsum(acc, s_part);
+    return team_rsum(acc, t, s_part);
 }
 
+// Loads and stores coherent across the device (agent-scope atomics: they
+// reach the memory side, past the per-XCD L2), for columns handed from one
+// workgroup to another inside a launch
+HCN_DEV double ld_device(const double *p) {
+    return __longlong_as_double(
+        __hip_atomic_load((long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+HCN_DEV void st_device(double *p, double v) {
+    __hip_atomic_store((long long *)p, __double_as_longlong(v), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// a *= iv in place; with `copy` (interleaved, global), the scaled rows also
+// go there with device-coherent stores
 template <class R>
-HCN_DEV void col_scale(double *a, const R &iv, int N) {
+HCN_DEV void col_scale(const Col &a, const R &iv, int N, int t, double *copy = nullptr) {
     constexpr int W = 2 * limbs<R>::P;
-    for (int i = threadIdx.x; i < N; i += BT) {
-        double *p = a + (size_t)i * W;
-        cstore(p, cscale(iv, cload<R>(p)));
+    for (int i = t; i < N; i += TEAM) {
+        const cx<R> v = cscale(iv, col_ld<R>(a, i));
+        col_st<R>(a, i, v);
+        if (copy) {
+            double tmp[W];
+            cstore(tmp, v);
+#pragma unroll
+            for (int l = 0; l < W; ++l) st_device(copy + (size_t)i * W + l, tmp[l]);
+        }
     }
 }
 
-// r_jj = ||a_j||, 1/r_jj and q_j = a_j / r_jj on the column at `aj`; writes
-// R[j][j] and inv[j].  Every lane holds the same squared norm, so every lane
-// forms r_jj and 1/r_jj itself (the same bits; no broadcast).  Returns false
-// (on every lane) for a singular column.
+// r_jj = ||a_j|| and 1/r_jj from the squared norm s (the same bits on every
+// lane of the team); stores R[j][j] and inv[j] (lane t == 0).  False for a
+// singular column.
 template <class R>
-HCN_DEV bool col_normalise(const MgsArgs &a, int b, int j, double *aj, R *s_part) {
+HCN_DEV bool col_pivot(const MgsArgs &a, int b, int j, const R &s, int t, R *iv_out) {
     constexpr int P = limbs<R>::P;
     constexpr int W = 2 * P;
-    const R s = col_norm2<R>(aj, a.N, s_part);
     const R rkk = sqrt(s);
     if (!(lead(rkk) > 0.0) || !rfinite(rkk)) return false;
     const R iv = div(rmake<R>(1.0), rkk);
-    if (threadIdx.x == 0) {
+    if (t == 0) {
         rstore(a.inv + (size_t)b * a.inv_pstride + (size_t)j * P, iv);
         const cx<R> rc{rkk, rmake<R>(0.0)};
         cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * a.n + j) * W, rc);
     }
-    col_scale<R>(aj, iv, a.N);
+    *iv_out = iv;
+    return true;
+}
+
+// r_jj, 1/r_jj and q_j = a_j / r_jj on the column at `aj` by the one-team
+// workgroup; false (on every lane) for a singular column
+template <class R>
+HCN_DEV bool col_normalise(const MgsArgs &a, int b, int j, double *aj, R *s_part) {
+    const int t = threadIdx.x;
+    const Col c = interleaved<R>(aj);
+    R iv;
+    if (!col_pivot<R>(a, b, j, col_norm2<R>(c, a.N, t, s_part), t, &iv)) return false;
+    col_scale<R>(c, iv, a.N, t);
     return true;
 }
 
@@ -169,10 +238,11 @@ __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
     double *aj = col_ptr(a, b, j);
     if (k >= 0) {
         const double *qk = col_ptr(a, b, k);
-        const cx<R> r = col_dot<R>(qk, aj, a.N, s_part);
+        const Col q = interleaved<R>((double *)qk), c = interleaved<R>(aj);
+        const cx<R> r = col_dot<R>(q, c, a.N, threadIdx.x, s_part);
         if (threadIdx.x == 0)
             cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * a.n + k) * W, r);
-        col_axpy<R>(qk, aj, r, a.N);
+        col_axpy<R>(q, c, r, a.N, threadIdx.x);
     }
     if (j == k + 1 && j < a.n) {
         if (!col_normalise<R>(a, b, j, aj, s_rpart) && threadIdx.x == 0) sing[b] = 1;
@@ -185,10 +255,11 @@ __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
 // sing[b]: 0 running, 1 singular column, 2 a wait timed out
 constexpr int PIPE_SINGULAR = 1, PIPE_TIMEOUT = 2;
 
-// Thread 0 waits (bounded) until flags[k] is set or the problem stopped;
-// the acquire fence then makes the published column visible to the
-// workgroup.  Returns false (on every thread) when the problem stopped.
-HCN_DEV bool pipe_wait(const int *flag, int *stop_word, long spin_limit, int *s_go) {
+// Thread 0 waits (bounded) until flags[k] is set or the problem stopped.
+// The published column is then read with device-coherent loads, issued
+// after the flag was seen.  Returns false (on every thread) when the
+// problem stopped.
+HCN_DEV bool pipe_wait(int *flag, int *stop_word, long spin_limit, int *s_go) {
     if (threadIdx.x == 0) {
         int go = 1;
         long spins = 0;
@@ -204,7 +275,6 @@ HCN_DEV bool pipe_wait(const int *flag, int *stop_word, long spin_limit, int *s_
             }
             __builtin_amdgcn_s_sleep(2);
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *s_go = go;
     }
     __syncthreads();
@@ -212,51 +282,53 @@ HCN_DEV bool pipe_wait(const int *flag, int *stop_word, long spin_limit, int *s_
 }
 
 template <class R>
-__global__ __launch_bounds__(BT) void k_mgs_pipe(MgsArgs a, int *sing, int *flags, long spin_limit) {
-    constexpr int P = limbs<R>::P;
-    constexpr int W = 2 * P;
-    extern __shared__ double lds[];  // own columns [c][N][W]
-    __shared__ cx<R> s_part[BT / 64];
-    __shared__ R s_rpart[BT / 64];
+__global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *flags, long spin_limit) {
+    constexpr int W = 2 * limbs<R>::P;
+    extern __shared__ double lds[];  // own columns [c][W][N] (planar), then q_k [W][N]
+    __shared__ cx<R> s_part[TEAM / 64];
+    __shared__ R s_rpart[TEAM / 64];
     __shared__ int s_go;
     const int b = blockIdx.y;
     if (!problem_live(a, b)) return;
-    const int G = gridDim.x, w = blockIdx.x, n = a.n, N = a.N;
-    const size_t cst = (size_t)N * W;
+    const int G = gridDim.x, w = blockIdx.x, n = a.n, N = a.N, t = threadIdx.x;
     if (w > n) return;
     const int mine = (n - w) / G + 1;  // columns w, w + G, ...
+    const size_t cst = (size_t)N * W;
+    double *qs = lds + (size_t)mine * cst;  // each lane's rows of the last q_k received
     int *flg = flags + (size_t)b * (n + 1);
     int *stop = sing + b;
     for (int c = 0; c < mine; ++c) {
         const double *src = col_ptr(a, b, w + c * G);
-        for (size_t t = threadIdx.x; t < cst; t += BT) lds[(size_t)c * cst + t] = src[t];
+        for (size_t e = t; e < cst; e += TEAM) lds[(size_t)c * cst + (e % W) * N + e / W] = src[e];
     }
     __syncthreads();
-    // column j (owned, in LDS slot c), fully projected: r_jj, 1/r_jj, q_j;
-    // q_j goes to its place in A and its flag is raised.  False: singular.
+    auto own = [&](int c) { return planar(lds + (size_t)c * cst, N); };
+    const Col qs_col = planar(qs, N);
+    // own column j (slot c), fully projected: r_jj, 1/r_jj and q_j, written
+    // to LDS and to its place in A, then its flag.  False: singular.
     auto publish = [&](int c) -> bool {
         const int j = w + c * G;
-        double *aj = lds + (size_t)c * cst;
-        if (!col_normalise<R>(a, b, j, aj, s_rpart)) {
-            if (threadIdx.x == 0)
-                __hip_atomic_store(stop, PIPE_SINGULAR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const Col aj = own(c);
+        R iv;
+        if (!col_pivot<R>(a, b, j, col_norm2<R>(aj, N, t, s_rpart), t, &iv)) {
+            if (t == 0) __hip_atomic_store(stop, PIPE_SINGULAR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
-        __syncthreads();  // the scaled rows, written row-wise, are copied element-wise
-        double *dst = col_ptr(a, b, j);
-        for (size_t t = threadIdx.x; t < cst; t += BT) dst[t] = aj[t];
-        // the workgroup's stores complete before the barrier; the release
-        // store writes them back beyond this XCD's L2 before the flag
+        col_scale<R>(aj, iv, N, t, col_ptr(a, b, j));
+        // every wave's stores complete (an agent-scope release by each:
+        // a workgroup barrier alone does not wait for global stores), then
+        // the flag
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_store(flg + j, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (t == 0) __hip_atomic_store(flg + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         return true;
     };
     bool live = true;
     if (w == 0 && n > 0) live = publish(0);
     for (int k = 0; k < n && live; ++k) {
-        const double *qk;
+        Col qk;
         if (k % G == w) {
-            qk = lds + (size_t)(k / G) * cst;
+            qk = own(k / G);
         } else {
             // q_k is needed only while this workgroup has a column beyond k
             if (k >= w && w + ((k - w) / G + 1) * G > n) break;
@@ -264,28 +336,31 @@ __global__ __launch_bounds__(BT) void k_mgs_pipe(MgsArgs a, int *sing, int *flag
                 live = false;
                 break;
             }
-            // each lane reads its own rows of the published q_k (the first
-            // column's dot product fetches them, later ones hit the caches)
-            qk = col_ptr(a, b, k);
+            // each lane fetches its own rows of the published q_k with
+            // device-coherent loads into its rows of the staging column
+            // (read back only by the same lane: no barrier)
+            const double *src = col_ptr(a, b, k);
+            for (int i = t; i < N; i += TEAM)
+#pragma unroll
+                for (int l = 0; l < W; ++l) qs[(size_t)l * N + i] = ld_device(src + (size_t)i * W + l);
+            qk = qs_col;
         }
         // own columns j > k in increasing order (column k+1 first)
         const int c0 = k < w ? 0 : (k - w) / G + 1;
         for (int c = c0; c < mine && live; ++c) {
             const int j = w + c * G;
-            double *aj = lds + (size_t)c * cst;
-            const cx<R> r = col_dot<R>(qk, aj, N, s_part);
-            if (threadIdx.x == 0)
-                cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * n + k) * W, r);
-            col_axpy<R>(qk, aj, r, N);
+            const Col aj = own(c);
+            const cx<R> r = col_dot<R>(qk, aj, N, t, s_part);
+            if (t == 0) cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * n + k) * W, r);
+            col_axpy<R>(qk, aj, r, N, t);
             if (j == k + 1 && j < n) live = publish(c);
         }
     }
     // the projected right-hand side (column n) goes back to its place
     if (live && n % G == w) {
-        __syncthreads();
-        const double *src = lds + (size_t)(n / G) * cst;
+        const Col src = own(n / G);
         double *dst = col_ptr(a, b, n);
-        for (size_t t = threadIdx.x; t < cst; t += BT) dst[t] = src[t];
+        for (int i = t; i < N; i += TEAM) cstore(dst + (size_t)i * W, col_ld<R>(src, i));
     }
 }
 
@@ -386,8 +461,12 @@ __global__ void k_zero_int(int *p, int count) {
 }
 
 // workgroups of the pipelined variant for one problem (0: it does not fit):
-// at most one per CU-slot the occupancy calculator allows with the LDS of
-// its columns, and B of them must be resident together
+// the columns dealt round G workgroups, each holding its columns in LDS,
+// all B x G of them resident at once.  G starts at one workgroup per CU per
+// problem (several problems then share CUs, their chains interleaving) and
+// halves until the B x G workgroups fit the device's residency.
+constexpr size_t PIPE_MAX_DYN_LDS = 159 * 1024;
+
 template <class R>
 static int pipe_groups(const MgsArgs &a, size_t *lds_out) {
     static int cus = 0;
@@ -398,19 +477,27 @@ static int pipe_groups(const MgsArgs &a, size_t *lds_out) {
             return 0;
     }
     const size_t cst = (size_t)a.N * 2 * limbs<R>::P * sizeof(double);
-    int G = std::min(cus / std::max(a.B, 1), a.n + 1);
-    if (G < 1) return 0;
-    const int mine = a.n / G + 1;
-    const size_t lds = (size_t)mine * cst;
-    if (lds > 160 * 1024) return 0;
-    (void)hipFuncSetAttribute((const void *)k_mgs_pipe<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)lds);
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mgs_pipe<R>, BT, lds) != hipSuccess ||
-        per_cu < 1)
-        return 0;
-    *lds_out = lds;
-    return G;
+    for (int G = std::min(cus, a.n + 1); G >= 1; G /= 2) {
+        const int mine = a.n / G + 1;
+        const size_t lds = (size_t)(mine + 1) * cst;
+        // the LDS of a CU (160 KB) holds the dynamic part and the kernel's
+        // own few hundred bytes of reduction slots
+        if (lds > PIPE_MAX_DYN_LDS) return 0;
+        if (hipFuncSetAttribute((const void *)k_mgs_pipe<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds) != hipSuccess) {
+            (void)hipGetLastError();
+            return 0;
+        }
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mgs_pipe<R>, TEAM, lds) !=
+            hipSuccess)
+            return 0;
+        if ((long)per_cu * cus >= (long)G * a.B) {
+            *lds_out = lds;
+            return G;
+        }
+    }
+    return 0;
 }
 
 // bounded waits: about a second of polling before a wait gives up
@@ -435,11 +522,16 @@ static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s)
             long spin = PIPE_SPIN_LIMIT;
             void *args[] = {&av, &sing, &flags, &spin};
             const hipError_t e = hipLaunchCooperativeKernel((const void *)k_mgs_pipe<R>, dim3(G, a.B),
-                                                            dim3(BT), args, (unsigned)pipe_lds, s);
-            if (e != hipSuccess) return (int)e;
-        } else if (variant == 4) {
+                                                            dim3(TEAM), args, (unsigned)pipe_lds, s);
+            // a launch the device cannot take whole goes right-looking
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                variant = 2;
+            }
+        }
+        if (variant == 4) {
             launch_tiled<R>(a, sing, s);
-        } else {
+        } else if (variant == 2) {
             hipLaunchKernelGGL(k_mgs_rl<R>, dim3(1, a.B), dim3(BT), 0, s, a, -1, sing);
             for (int k = 0; k < a.n; ++k)
                 hipLaunchKernelGGL(k_mgs_rl<R>, dim3(a.n - k, a.B), dim3(BT), 0, s, a, k, sing);

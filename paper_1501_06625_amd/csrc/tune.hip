@@ -125,7 +125,7 @@ int hcn_autotune(hcn_sys sys, int B, const double *x_dev, int reps, int *best_gr
                  int *best_lds, double *best_ms, void *stream) {
     if (!sys || !x_dev || B < 1 || reps < 1) return HCN_EINVAL;
     hcn_sys_info_t info;
-    hcn_sys_info(sys, &info);
+    if (hcn_sys_info(sys, &info) != HCN_OK) return HCN_EINVAL;
     const int P = info.P, N = info.N, n = info.n;
     hipStream_t s = (hipStream_t)stream;
     const size_t xbytes = (size_t)B * n * 2 * P * sizeof(double);
