@@ -64,17 +64,18 @@ HBM_PEAK_GBS = 8000.0
 # COUNTERS_DIGEST[kernel] (source_digest(kernel), over KERNEL_SOURCES[kernel]);
 # other sources report traffic null.
 HBM_COUNTERS_KIB = {
-    "mgs": {(8, 0): (914308.5, 5363301.7), (8, 1): (274850.0, 205529.5), (8, 2): (274997.6, 206119.3),
-            (8, 3): (437086.8, 542545.7), (16, 0): (876101.0, 4627639.1), (16, 1): (274880.8, 205993.9),
-            (16, 2): (275024.4, 205809.6), (16, 3): (451486.8, 540727.1), (32, 0): (793216.0, 3988355.4),
-            (32, 1): (274887.6, 207304.7), (32, 3): (479989.7, 537147.9)},
-    "eval_monomials": (38055.1, 5570560.0), "eval_sums": (3648677.0, 393871.9)}
+    "mgs": {(8, 0): (918147.4, 5360362.0), (8, 1): (274855.4, 205534.4), (8, 2): (274997.8, 206143.1),
+            (8, 3): (437179.1, 542292.4), (16, 0): (893944.9, 4636952.2), (16, 1): (274880.6, 205976.1),
+            (16, 2): (275024.1, 205808.5), (16, 3): (453015.0, 540628.5), (32, 0): (798519.7, 3995524.2),
+            (32, 1): (274889.4, 207216.3), (32, 3): (481071.6, 537031.1)},
+    "eval_monomials": (38501.1, 5570560.0), "eval_sums": (3652239.9, 393933.1)}
 KERNEL_SOURCES = {
     "mgs": ("mgs.hip", "mgs_common.hpp", "mp.hpp", "internal.hpp", "tune.hip"),
     "eval_monomials": ("eval.hip", "eval_body.hpp", "mp.hpp", "internal.hpp"),
     "eval_sums": ("eval.hip", "eval_body.hpp", "mp.hpp", "internal.hpp"),
 }
-COUNTERS_DIGEST = {}
+COUNTERS_DIGEST = {"mgs": "098b5eda59229865", "eval_monomials": "28832b224f059a8e",
+                   "eval_sums": "28832b224f059a8e"}
 MGS_PIN = None  # (lane group, storage) from --mgs-group / --mgs-storage, else autotuned
 FETCH_CAL, WRITE_CAL = 10485760 / (5131.5 * 1024), 1.0
 _T0 = time.time()
