@@ -152,9 +152,9 @@ int hcn_mgs_solve(int B, int N, int n, int P, double *A_dev, double *b_dev,
  * column, held in registers: 2 ceil(n/T) launches), 5 pipelined (one
  * cooperative launch: the columns stay in the LDS of persistent workgroups,
  * column j in workgroup j mod G; the owner of a column publishes q_k in
- * place with a flag as soon as it is projected and normalised, and every
- * workgroup applies the q_k in order to its own later columns, the next
- * column first).  1 and 4 differ from 2 only by the rounding of their
+ * place as soon as it is projected and normalised, and every workgroup
+ * applies the q_k in order to its own later columns, the next column
+ * first).  1 and 4 differ from 2 only by the rounding of their
  * reductions; 5 gives the bits of 2.  4 falls back to 2 when N > 512 (DD,
  * FP64) or N > 256 (QD); 5 falls back to 2 when the columns of one
  * workgroup do not fit its LDS or the workgroups cannot all be resident.
@@ -165,6 +165,13 @@ int hcn_set_mgs_variant(int variant);
 /* Panel width T of variant 4 (process-wide), 1 <= T <= 16; default 16.
  * EINVAL outside that range. */
 int hcn_set_mgs_panel(int T);
+
+/* Bound on each wait of variant 5 (process-wide), in polls of the awaited
+ * words (about a microsecond each); default 4194304 (seconds).  A wait that
+ * runs out stops the problem, which then reports HCN_EDEVICE; a small
+ * bound lets a test take that path with every kernel ending normally.
+ * EINVAL for polls < 0. */
+int hcn_set_mgs_wait_limit(long long polls);
 
 /* How the monomial kernels form the common factor of R1 (process-wide;
  * default 1): 1 the same products in every lane of a wavefront (a product by

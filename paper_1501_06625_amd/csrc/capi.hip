@@ -1078,6 +1078,12 @@ int hcn_set_mgs_panel(int T) {
     return HCN_OK;
 }
 
+int hcn_set_mgs_wait_limit(long long polls) {
+    if (polls < 0) return fail(HCN_EINVAL, "hcn_set_mgs_wait_limit: polls must be >= 0");
+    set_mgs_wait_limit(polls);
+    return HCN_OK;
+}
+
 int hcn_elementwise(int op, int P, int count, const double *a, const double *b, double *out,
                     void *stream) {
     if (P != 1 && P != 2 && P != 4) return fail(HCN_EINVAL, "hcn_elementwise: P must be 1, 2 or 4");

@@ -146,6 +146,7 @@ int launch_mgs_big(int P, const MgsArgs &a, int variant, int *ints_dev, hipStrea
 int mgs_tiled_rpl(int N, int P);
 int mgs_panel_width();
 void set_mgs_panel_width(int T);
+void set_mgs_wait_limit(long long polls);
 // the device tables of a loaded system (capi.hip); references held by
 // batches and queued requests, the tables freed with the last
 SysView sys_view(hcn_sys s);

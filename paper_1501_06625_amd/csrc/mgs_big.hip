@@ -17,18 +17,22 @@
 // Pipelined (one cooperative launch): a persistent workgroup per slice of
 // columns (column j belongs to workgroup j mod G and stays in its LDS for
 // the whole factorisation; one workgroup per CU, so the chain of column
-// steps always has a CU of its own).  The owner of column k normalises it
-// and publishes q_k in place in A (the column's final value) with a flag;
-// every workgroup waits for the flags in order, reads q_k from A and
-// projects it out of its own later columns, the next column first, so that
-// the owner of column k+1 can publish q_{k+1} while the others still work
-// on q_k (look-ahead).  The column operations are the right-looking
-// variant's (same lanes, rows, butterflies and order), so the results are
-// bitwise the same; the trailing matrix never leaves LDS and the step
-// boundaries cost a flag instead of a launch.  Waits are bounded: a wait
-// that times out (a workgroup not resident, which the cooperative launch
-// rules out) or a singular column stops every workgroup of the problem, and
-// the epilogue reports the problem as failed (HCN_EDEVICE or ESINGULAR).
+// steps always has a CU of its own).  At the start every workgroup marks
+// the places of its columns in A empty (a signalling-NaN pattern) and the
+// workgroups of a problem meet once.  The owner of column k normalises it
+// and publishes q_k in place in A (the column's final value) with
+// device-coherent stores: the data are their own flag, with no fence or
+// flag word on the chain.  Every workgroup takes q_k in order, each lane
+// polling its own rows until none is empty, and projects it out of its own
+// later columns, the next column first, so that the owner of column k+1 can
+// publish q_{k+1} while the others still work on q_k (look-ahead).  The
+// column operations are the right-looking variant's (same lanes, rows,
+// butterflies and order), so the results are bitwise the same; the trailing
+// matrix never leaves LDS and the step boundaries cost no launch.  Waits
+// are bounded: a wait that times out (a workgroup not resident, which the
+// cooperative launch rules out) or a singular column stops every workgroup
+// of the problem, and the epilogue reports the problem as failed
+// (HCN_EDEVICE or ESINGULAR).
 //
 // Tiled (panel width T; mgs_tiled.hpp): the columns are taken T at a time.
 // A panel launch factors columns k0..k0+T-1 in one workgroup of T
@@ -60,8 +64,17 @@ constexpr int BT = MGS_THREADS;
 // (its part of the sum is zero) but keeps the barriers.
 constexpr int TEAM = MGS_THREADS;
 
+// The partial sums go through a ring of two slots, taken in turn (`ph`
+// flips at every call; every lane of the team makes the same calls): a slot
+// is written again only two sums later, after the barrier of the sum in
+// between, which every lane passes only once it has read the slot.  One
+// barrier per sum.  A complex slot holds two sums' partials (team_csum2).
+constexpr int CSLOT = 2 * (TEAM / 64);
+
 template <class R>
-HCN_DEV cx<R> team_csum(cx<R> v, int t, cx<R> *s_part) {
+HCN_DEV cx<R> team_csum(cx<R> v, int t, cx<R> *ring, int &ph) {
+    cx<R> *s_part = ring + ph * CSLOT;
+    ph ^= 1;
     const int lane = t & 63;
     v = group_csum<R, 64>(v, lane);
     if (lane == 0) s_part[t >> 6] = v;
@@ -69,12 +82,36 @@ HCN_DEV cx<R> team_csum(cx<R> v, int t, cx<R> *s_part) {
     cx<R> s = s_part[0];
 #pragma unroll
     for (int w = 1; w < TEAM / 64; ++w) s = cadd(s, s_part[w]);
-    __syncthreads();
     return s;
 }
 
+// two independent sums side by side, each in team_csum's order
 template <class R>
-HCN_DEV R team_rsum(R v, int t, R *s_part) {
+HCN_DEV void team_csum2(cx<R> &v0, cx<R> &v1, int t, cx<R> *ring, int &ph) {
+    cx<R> *s_part = ring + ph * CSLOT;
+    ph ^= 1;
+    const int lane = t & 63;
+    v0 = group_csum<R, 64>(v0, lane);
+    v1 = group_csum<R, 64>(v1, lane);
+    if (lane == 0) {
+        s_part[t >> 6] = v0;
+        s_part[TEAM / 64 + (t >> 6)] = v1;
+    }
+    __syncthreads();
+    cx<R> s0 = s_part[0], s1 = s_part[TEAM / 64];
+#pragma unroll
+    for (int w = 1; w < TEAM / 64; ++w) {
+        s0 = cadd(s0, s_part[w]);
+        s1 = cadd(s1, s_part[TEAM / 64 + w]);
+    }
+    v0 = s0;
+    v1 = s1;
+}
+
+template <class R>
+HCN_DEV R team_rsum(R v, int t, R *ring, int &ph) {
+    R *s_part = ring + ph * (TEAM / 64);
+    ph ^= 1;
     const int lane = t & 63;
     v = group_sum<R, 64>(v, lane);
     if (lane == 0) s_part[t >> 6] = v;
@@ -82,9 +119,17 @@ HCN_DEV R team_rsum(R v, int t, R *s_part) {
     R s = s_part[0];
 #pragma unroll
     for (int w = 1; w < TEAM / 64; ++w) s = add(s, s_part[w]);
-    __syncthreads();
     return s;
 }
+
+// the two rings of a team's sums (complex dot products, real squared norms)
+template <class R>
+struct TeamSums {
+    cx<R> *c;
+    R *r;
+    int pc, pr;
+    HCN_DEV TeamSums(cx<R> *c_ring, R *r_ring) : c(c_ring), r(r_ring), pc(0), pr(0) {}
+};
 
 // A column as rows of complex numbers: limb l of row i at p[i * step + l * ld].
 // In global memory a column is interleaved (step = 2P, ld = 1, the
@@ -121,7 +166,7 @@ HCN_DEV void col_st(const Col &c, int i, const cx<R> &x) {
 
 // q^H a over the column
 template <class R>
-HCN_DEV cx<R> col_dot(const Col &q, const Col &a, int N, int t, cx<R> *s_part, bool act = true) {
+HCN_DEV cx<R> col_dot(const Col &q, const Col &a, int N, int t, TeamSums<R> &ts, bool act = true) {
     cx<R> acc = czero<R>();
     bool first = true;
     if (act) {
@@ -131,7 +176,7 @@ HCN_DEV cx<R> col_dot(const Col &q, const Col &a, int N, int t, cx<R> *s_part, b
             first = false;
         }
     }
-    return team_csum(acc, t, s_part);
+    return team_csum(acc, t, ts.c, ts.pc);
 }
 
 template <class R>
@@ -139,8 +184,34 @@ HCN_DEV void col_axpy(const Col &q, const Col &a, const cx<R> &r, int N, int t) 
     for (int i = t; i < N; i += TEAM) col_st<R>(a, i, csub(col_ld<R>(a, i), cmul(r, col_ld<R>(q, i))));
 }
 
+// r0 = q^H a0, r1 = q^H a1 and a0 -= r0 q, a1 -= r1 q side by side: two
+// independent chains for the scheduler, each in the order of col_dot and
+// col_axpy (the same bits)
 template <class R>
-HCN_DEV R col_norm2(const Col &a, int N, int t, R *s_part, bool act = true) {
+HCN_DEV void col_update2(const Col &q, const Col &a0, const Col &a1, int N, int t, TeamSums<R> &ts,
+                         cx<R> &r0, cx<R> &r1) {
+    cx<R> acc0 = czero<R>(), acc1 = czero<R>();
+    bool first = true;
+    for (int i = t; i < N; i += TEAM) {
+        const cx<R> qi = col_ld<R>(q, i);
+        const cx<R> v0 = cmul_conj(qi, col_ld<R>(a0, i));
+        const cx<R> v1 = cmul_conj(qi, col_ld<R>(a1, i));
+        acc0 = first ? v0 : cadd(acc0, v0);
+        acc1 = first ? v1 : cadd(acc1, v1);
+        first = false;
+    }
+    team_csum2(acc0, acc1, t, ts.c, ts.pc);
+    r0 = acc0;
+    r1 = acc1;
+    for (int i = t; i < N; i += TEAM) {
+        const cx<R> qi = col_ld<R>(q, i);
+        col_st<R>(a0, i, csub(col_ld<R>(a0, i), cmul(r0, qi)));
+        col_st<R>(a1, i, csub(col_ld<R>(a1, i), cmul(r1, qi)));
+    }
+}
+
+template <class R>
+HCN_DEV R col_norm2(const Col &a, int N, int t, TeamSums<R> &ts, bool act = true) {
     R acc = rmake<R>(0.0);
     bool first = true;
     if (act) {
@@ -150,7 +221,7 @@ HCN_DEV R col_norm2(const Col &a, int N, int t, R *s_part, bool act = true) {
             first = false;
         }
     }
-    return team_rsum(acc, t, s_part);
+    return team_rsum(acc, t, ts.r, ts.pr);
 }
 
 // Loads and stores coherent across the device (agent-scope atomics: they
@@ -204,11 +275,11 @@ HCN_DEV bool col_pivot(const MgsArgs &a, int b, int j, const R &s, int t, R *iv_
 // r_jj, 1/r_jj and q_j = a_j / r_jj on the column at `aj` by the one-team
 // workgroup; false (on every lane) for a singular column
 template <class R>
-HCN_DEV bool col_normalise(const MgsArgs &a, int b, int j, double *aj, R *s_part) {
+HCN_DEV bool col_normalise(const MgsArgs &a, int b, int j, double *aj, TeamSums<R> &ts) {
     const int t = threadIdx.x;
     const Col c = interleaved<R>(aj);
     R iv;
-    if (!col_pivot<R>(a, b, j, col_norm2<R>(c, a.N, t, s_part), t, &iv)) return false;
+    if (!col_pivot<R>(a, b, j, col_norm2<R>(c, a.N, t, ts), t, &iv)) return false;
     col_scale<R>(c, iv, a.N, t);
     return true;
 }
@@ -229,8 +300,9 @@ HCN_DEV bool problem_live(const MgsArgs &a, int b) {
 template <class R>
 __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
     constexpr int W = 2 * limbs<R>::P;
-    __shared__ cx<R> s_part[BT / 64];
-    __shared__ R s_rpart[BT / 64];
+    __shared__ cx<R> s_part[2 * CSLOT];
+    __shared__ R s_rpart[2 * (BT / 64)];
+    TeamSums<R> ts(s_part, s_rpart);
     const int b = blockIdx.y;
     if (!problem_live(a, b) || sing[b]) return;
     const int j = (k < 0) ? 0 : k + 1 + (int)blockIdx.x;
@@ -239,13 +311,13 @@ __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
     if (k >= 0) {
         const double *qk = col_ptr(a, b, k);
         const Col q = interleaved<R>((double *)qk), c = interleaved<R>(aj);
-        const cx<R> r = col_dot<R>(q, c, a.N, threadIdx.x, s_part);
+        const cx<R> r = col_dot<R>(q, c, a.N, threadIdx.x, ts);
         if (threadIdx.x == 0)
             cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * a.n + k) * W, r);
         col_axpy<R>(q, c, r, a.N, threadIdx.x);
     }
     if (j == k + 1 && j < a.n) {
-        if (!col_normalise<R>(a, b, j, aj, s_rpart) && threadIdx.x == 0) sing[b] = 1;
+        if (!col_normalise<R>(a, b, j, aj, ts) && threadIdx.x == 0) sing[b] = 1;
     }
 }
 
@@ -255,10 +327,49 @@ __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
 // sing[b]: 0 running, 1 singular column, 2 a wait timed out
 constexpr int PIPE_SINGULAR = 1, PIPE_TIMEOUT = 2;
 
-// Thread 0 waits (bounded) until flags[k] is set or the problem stopped.
-// The published column is then read with device-coherent loads, issued
-// after the flag was seen.  Returns false (on every thread) when the
-// problem stopped.
+// Bit pattern of a not-yet-published word of a column: a signalling NaN.
+// Published words are results of floating-point arithmetic (q_k = a_k / r_kk
+// limb by limb), which never yields a signalling NaN, so a word differing
+// from this pattern holds its final value.
+constexpr long long PIPE_EMPTY = 0x7FF0DEAD5EA1BEEFLL;
+
+HCN_DEV long long ld_device_bits(const double *p) {
+    return __hip_atomic_load((long long *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One lane's wait for its rows of a published column: the data are their
+// own flag.  The lane loads its words of the column at src (interleaved)
+// with device-coherent loads into its rows of the staging column qs
+// (planar), every word at every poll, until no word is empty.  Bounded:
+// false once the problem stopped (stop word set by another workgroup) or
+// the spin limit passed (the lane then sets the stop word to PIPE_TIMEOUT).
+template <class R>
+HCN_DEV bool pipe_fetch(const double *src, double *qs, int N, int t, int *stop_word, long spin_limit) {
+    constexpr int W = 2 * limbs<R>::P;
+    if (t >= N) return true;
+    long spins = 0;
+    for (;;) {
+        bool all = true;
+        for (int i = t; i < N; i += TEAM)
+#pragma unroll
+            for (int l = 0; l < W; ++l) {
+                const long long v = ld_device_bits(src + (size_t)i * W + l);
+                all = all && v != PIPE_EMPTY;
+                qs[(size_t)l * N + i] = __longlong_as_double(v);
+            }
+        if (all) return true;
+        if (__hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return false;
+        if (++spins > spin_limit) {
+            __hip_atomic_store(stop_word, PIPE_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Thread 0's bounded wait until flags[k] is set or the problem stopped
+// (false on every thread then); the column's stores completed before its
+// flag was raised.
 HCN_DEV bool pipe_wait(int *flag, int *stop_word, long spin_limit, int *s_go) {
     if (threadIdx.x == 0) {
         int go = 1;
@@ -281,13 +392,19 @@ HCN_DEV bool pipe_wait(int *flag, int *stop_word, long spin_limit, int *s_go) {
     return *s_go != 0;
 }
 
+// Workgroups whose next columns are this close to column k poll q_k's data
+// themselves; the others wait for its flag (fewer loads on the lines being
+// written)
+constexpr int PIPE_EAGER = 2;
+
 template <class R>
-__global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *flags, long spin_limit) {
+__global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *arrived, int *flags, long spin_limit) {
     constexpr int W = 2 * limbs<R>::P;
     extern __shared__ double lds[];  // own columns [c][W][N] (planar), then q_k [W][N]
-    __shared__ cx<R> s_part[TEAM / 64];
-    __shared__ R s_rpart[TEAM / 64];
+    __shared__ cx<R> s_part[2 * CSLOT];
+    __shared__ R s_rpart[2 * (TEAM / 64)];
     __shared__ int s_go;
+    TeamSums<R> ts(s_part, s_rpart);
     const int b = blockIdx.y;
     if (!problem_live(a, b)) return;
     const int G = gridDim.x, w = blockIdx.x, n = a.n, N = a.N, t = threadIdx.x;
@@ -295,29 +412,56 @@ __global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *fl
     const int mine = (n - w) / G + 1;  // columns w, w + G, ...
     const size_t cst = (size_t)N * W;
     double *qs = lds + (size_t)mine * cst;  // each lane's rows of the last q_k received
-    int *flg = flags + (size_t)b * (n + 1);
     int *stop = sing + b;
+    int *flg = flags + (size_t)b * (n + 1);
+    // own columns into LDS; their places in A (columns j < n, where q_j
+    // will be published) marked empty
     for (int c = 0; c < mine; ++c) {
-        const double *src = col_ptr(a, b, w + c * G);
+        double *src = col_ptr(a, b, w + c * G);
         for (size_t e = t; e < cst; e += TEAM) lds[(size_t)c * cst + (e % W) * N + e / W] = src[e];
+        if (w + c * G < n) {
+            __syncthreads();  // the column is read whole before it is marked
+            for (size_t e = t; e < cst; e += TEAM) st_device(src + e, __longlong_as_double(PIPE_EMPTY));
+        }
+    }
+    // every workgroup of the problem has marked its columns before any
+    // reads one: each wave's stores complete (an agent-scope release), then
+    // the workgroup's arrival is counted and all G awaited (bounded)
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (t == 0) {
+        int *cnt = arrived + b;
+        __hip_atomic_fetch_add(cnt, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int go = 1;
+        long spins = 0;
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < G) {
+            if (++spins > spin_limit) {
+                __hip_atomic_store(stop, PIPE_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                go = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        s_go = go;
     }
     __syncthreads();
+    if (!s_go) return;
     auto own = [&](int c) { return planar(lds + (size_t)c * cst, N); };
     const Col qs_col = planar(qs, N);
     // own column j (slot c), fully projected: r_jj, 1/r_jj and q_j, written
-    // to LDS and to its place in A, then its flag.  False: singular.
+    // to LDS and to its place in A (which publishes it to the polling
+    // workgroups), then, once every wave's stores have completed (an
+    // agent-scope release; a workgroup barrier alone does not wait for
+    // global stores), its flag.  False: singular.
     auto publish = [&](int c) -> bool {
         const int j = w + c * G;
         const Col aj = own(c);
         R iv;
-        if (!col_pivot<R>(a, b, j, col_norm2<R>(aj, N, t, s_rpart), t, &iv)) {
+        if (!col_pivot<R>(a, b, j, col_norm2<R>(aj, N, t, ts), t, &iv)) {
             if (t == 0) __hip_atomic_store(stop, PIPE_SINGULAR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
         col_scale<R>(aj, iv, N, t, col_ptr(a, b, j));
-        // every wave's stores complete (an agent-scope release by each:
-        // a workgroup barrier alone does not wait for global stores), then
-        // the flag
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
         if (t == 0) __hip_atomic_store(flg + j, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -332,28 +476,44 @@ __global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *fl
         } else {
             // q_k is needed only while this workgroup has a column beyond k
             if (k >= w && w + ((k - w) / G + 1) * G > n) break;
-            if (!pipe_wait(flg + k, stop, spin_limit, &s_go)) {
+            // q_k into the staging column, each lane its own rows (read back
+            // only by the same lane); the workgroup goes on only if every
+            // lane got its rows
+            const int next = k < w ? w : w + ((k - w) / G + 1) * G;  // first own column > k
+            bool ok = true;
+            if (next - k > PIPE_EAGER) ok = pipe_wait(flg + k, stop, spin_limit, &s_go);
+            if (ok) ok = pipe_fetch<R>(col_ptr(a, b, k), qs, N, t, stop, spin_limit);
+            if (__syncthreads_or(!ok)) {
                 live = false;
                 break;
             }
-            // each lane fetches its own rows of the published q_k with
-            // device-coherent loads into its rows of the staging column
-            // (read back only by the same lane: no barrier)
-            const double *src = col_ptr(a, b, k);
-            for (int i = t; i < N; i += TEAM)
-#pragma unroll
-                for (int l = 0; l < W; ++l) qs[(size_t)l * N + i] = ld_device(src + (size_t)i * W + l);
             qk = qs_col;
         }
-        // own columns j > k in increasing order (column k+1 first)
-        const int c0 = k < w ? 0 : (k - w) / G + 1;
-        for (int c = c0; c < mine && live; ++c) {
-            const int j = w + c * G;
-            const Col aj = own(c);
-            const cx<R> r = col_dot<R>(qk, aj, N, t, s_part);
+        // own columns j > k in increasing order: column k+1 (on the chain)
+        // first and alone, then the others two at a time
+        auto rstore = [&](int j, const cx<R> &r) {
             if (t == 0) cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * n + k) * W, r);
+        };
+        int c = k < w ? 0 : (k - w) / G + 1;
+        if (c < mine && w + c * G == k + 1) {
+            const Col aj = own(c);
+            const cx<R> r = col_dot<R>(qk, aj, N, t, ts);
+            rstore(k + 1, r);
             col_axpy<R>(qk, aj, r, N, t);
-            if (j == k + 1 && j < n) live = publish(c);
+            if (k + 1 < n) live = publish(c);
+            ++c;
+        }
+        for (; c + 1 < mine && live; c += 2) {
+            cx<R> r0, r1;
+            col_update2<R>(qk, own(c), own(c + 1), N, t, ts, r0, r1);
+            rstore(w + c * G, r0);
+            rstore(w + (c + 1) * G, r1);
+        }
+        if (c < mine && live) {
+            const Col aj = own(c);
+            const cx<R> r = col_dot<R>(qk, aj, N, t, ts);
+            rstore(w + c * G, r);
+            col_axpy<R>(qk, aj, r, N, t);
         }
     }
     // the projected right-hand side (column n) goes back to its place
@@ -500,13 +660,18 @@ static int pipe_groups(const MgsArgs &a, size_t *lds_out) {
     return 0;
 }
 
-// bounded waits: about a second of polling before a wait gives up
-constexpr long PIPE_SPIN_LIMIT = 1L << 22;
+// bounded waits: seconds of polling before a wait gives up
+static long g_wait_limit = 1L << 22;
+
+void set_mgs_wait_limit(long long polls) { g_wait_limit = (long)polls; }
 
 template <class R>
 static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s) {
-    // ints: sing[B], then (after 2B + 1) the column flags [B][n + 1]
+    // ints: sing[B], then (after 2B + 1) the pipelined variant's column
+    // flags [B][n + 1], then its arrival counters [B] in the words B + 1 ..
+    // 2B (free in that variant)
     int *sing = ints;
+    int *arrived = ints + a.B + 1;
     int *flags = ints + 2 * a.B + 1;
     size_t pipe_lds = 0;
     const int G = variant == 5 ? pipe_groups<R>(a, &pipe_lds) : 0;
@@ -519,8 +684,8 @@ static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s)
         ProfScope prof("mgs", s);
         if (variant == 5) {
             MgsArgs av = a;
-            long spin = PIPE_SPIN_LIMIT;
-            void *args[] = {&av, &sing, &flags, &spin};
+            long spin = g_wait_limit;
+            void *args[] = {&av, &sing, &arrived, &flags, &spin};
             const hipError_t e = hipLaunchCooperativeKernel((const void *)k_mgs_pipe<R>, dim3(G, a.B),
                                                             dim3(TEAM), args, (unsigned)pipe_lds, s);
             // a launch the device cannot take whole goes right-looking

@@ -64,7 +64,7 @@ EXPORTS = ["hcn_last_error", "hcn_version", "hcn_sys_load", "hcn_sys_free", "hcn
            "hcn_mgs_solve", "hcn_newton_ws_bytes", "hcn_newton_step", "hcn_newton_step_static",
            "hcn_newton",
            "hcn_track_ws_bytes", "hcn_track_paths", "hcn_elementwise", "hcn_profile_enable",
-           "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_set_chunk_bytes", "hcn_set_mon_uniform", "hcn_set_mon_tree", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
+           "hcn_set_mgs_variant", "hcn_set_mgs_panel", "hcn_set_mgs_wait_limit", "hcn_set_chunk_bytes", "hcn_set_mon_uniform", "hcn_set_mon_tree", "hcn_newton_mixed_ws_bytes", "hcn_newton_mixed",
            "hcn_tune_set", "hcn_tune_get", "hcn_tune_save", "hcn_tune_load", "hcn_autotune",
            "hcn_batch_create", "hcn_batch_destroy", "hcn_batch_device_bytes",
            "hcn_batch_last_error", "hcn_batch_add", "hcn_batch_release", "hcn_batch_set_split", "hcn_batch_set_persistent", "hcn_batch_step",
@@ -105,6 +105,7 @@ def _load():
     lib.hcn_profile_enable.argtypes = [ci]
     lib.hcn_set_mgs_variant.argtypes = [ci]
     lib.hcn_set_mgs_panel.argtypes = [ci]
+    lib.hcn_set_mgs_wait_limit.argtypes = [ctypes.c_longlong]
     lib.hcn_set_chunk_bytes.argtypes = [sz]
     lib.hcn_set_mon_uniform.argtypes = [ci]
     lib.hcn_set_mon_tree.argtypes = [ci]
@@ -431,6 +432,14 @@ def set_mgs_variant(variant: int) -> None:
 def set_mgs_panel(T: int) -> None:
     """Panel width of the tiled MGS variant (see hcn_set_mgs_panel)."""
     _check(_lib.hcn_set_mgs_panel(int(T)))
+
+
+MGS_WAIT_LIMIT = 1 << 22
+
+
+def set_mgs_wait_limit(polls: int) -> None:
+    """Bound on each wait of the pipelined MGS (see hcn_set_mgs_wait_limit)."""
+    _check(_lib.hcn_set_mgs_wait_limit(int(polls)))
 
 
 def set_mon_uniform(on: bool) -> None:

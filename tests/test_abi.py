@@ -59,6 +59,8 @@ def test_host_side_argument_errors():
     assert lib.hcn_batch_create(ctypes.byref(h), 1, 4, 8, 64, 4, ctypes.byref(ok), 1, 0) == hcn.EINVAL
     assert lib.hcn_set_mgs_panel(0) == hcn.EINVAL
     assert lib.hcn_set_mgs_panel(17) == hcn.EINVAL
+    assert lib.hcn_set_mgs_wait_limit(-1) == hcn.EINVAL
+    assert lib.hcn_set_mgs_wait_limit(hcn.MGS_WAIT_LIMIT) == hcn.OK
     assert lib.hcn_tune_set(2, 32, 16, 5) == hcn.EINVAL
     assert lib.hcn_batch_set_persistent(None, 1) == hcn.EINVAL
     assert lib.hcn_tune_set(2, 32, 12, 0) == hcn.EINVAL

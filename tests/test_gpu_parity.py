@@ -633,11 +633,32 @@ def test_mgs_big_singular(H):
     for v in (2, 4, 5):
         _, _, s = _solve_variant(H, v, A, b)
         assert s[0] == H.ESINGULAR
-    # and a first column of zeros (the pipelined variant stops before any flag)
+    # and a first column of zeros (the pipelined variant stops before it publishes any column)
     A[0, 0] = 0.0
     for v in (2, 5):
         _, _, s = _solve_variant(H, v, A, b)
         assert s[0] == H.ESINGULAR
+
+
+def test_mgs_pipelined_wait_limit(H):
+    """A pipelined solve whose waits run out (a bound of zero polls, set from
+    the host, so that every kernel still ends normally) reports HCN_EDEVICE
+    for its problem; with the default bound back, the next solve is whole
+    and gives the right-looking bits."""
+    P = 2
+    rng = np.random.default_rng(11)
+    A = _rand_matrix(rng, 300, 300, P)[None]
+    b = random_points(rng, 1, 300, P)
+    H.set_mgs_wait_limit(0)
+    try:
+        _, _, s = _solve_variant(H, 5, A, b)
+    finally:
+        H.set_mgs_wait_limit(H.MGS_WAIT_LIMIT)
+    assert s[0] == H.EDEVICE
+    d5, R5, s5 = _solve_variant(H, 5, A, b)
+    d2, R2, s2 = _solve_variant(H, 2, A, b)
+    assert s5[0] == 0 and s2[0] == 0
+    assert _bitwise_equal(d2, d5) and _bitwise_equal(R2, R5)
 
 
 def test_newton_step_sparse512_vs_oracle(H):
