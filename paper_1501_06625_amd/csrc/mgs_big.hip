@@ -78,7 +78,7 @@ HCN_DEV cx<R> team_csum(cx<R> v, int t, cx<R> *ring, int &ph) {
     const int lane = t & 63;
     v = group_csum<R, 64>(v, lane);
     if (lane == 0) s_part[t >> 6] = v;
-    __syncthreads();
+    lds_barrier();
     cx<R> s = s_part[0];
 #pragma unroll
     for (int w = 1; w < TEAM / 64; ++w) s = cadd(s, s_part[w]);
@@ -97,7 +97,7 @@ HCN_DEV void team_csum2(cx<R> &v0, cx<R> &v1, int t, cx<R> *ring, int &ph) {
         s_part[t >> 6] = v0;
         s_part[TEAM / 64 + (t >> 6)] = v1;
     }
-    __syncthreads();
+    lds_barrier();
     cx<R> s0 = s_part[0], s1 = s_part[TEAM / 64];
 #pragma unroll
     for (int w = 1; w < TEAM / 64; ++w) {
@@ -115,7 +115,7 @@ HCN_DEV R team_rsum(R v, int t, R *ring, int &ph) {
     const int lane = t & 63;
     v = group_sum<R, 64>(v, lane);
     if (lane == 0) s_part[t >> 6] = v;
-    __syncthreads();
+    lds_barrier();
     R s = s_part[0];
 #pragma unroll
     for (int w = 1; w < TEAM / 64; ++w) s = add(s, s_part[w]);
@@ -398,9 +398,9 @@ HCN_DEV bool pipe_wait(int *flag, int *stop_word, long spin_limit, int *s_go) {
 constexpr int PIPE_EAGER = 2;
 
 template <class R>
-__global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *arrived, int *flags, long spin_limit) {
+__global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *arrived, int *flags, long spin_limit, int qslots) {
     constexpr int W = 2 * limbs<R>::P;
-    extern __shared__ double lds[];  // own columns [c][W][N] (planar), then q_k [W][N]
+    extern __shared__ double lds[];  // own columns [c][W][N] (planar), then qslots staging columns
     __shared__ cx<R> s_part[2 * CSLOT];
     __shared__ R s_rpart[2 * (TEAM / 64)];
     __shared__ int s_go;
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *ar
     if (w > n) return;
     const int mine = (n - w) / G + 1;  // columns w, w + G, ...
     const size_t cst = (size_t)N * W;
-    double *qs = lds + (size_t)mine * cst;  // each lane's rows of the last q_k received
+    double *qs0 = lds + (size_t)mine * cst;  // q_k received, in slot k mod qslots
     int *stop = sing + b;
     int *flg = flags + (size_t)b * (n + 1);
     // own columns into LDS; their places in A (columns j < n, where q_j
@@ -447,7 +447,6 @@ __global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *ar
     __syncthreads();
     if (!s_go) return;
     auto own = [&](int c) { return planar(lds + (size_t)c * cst, N); };
-    const Col qs_col = planar(qs, N);
     // own column j (slot c), fully projected: r_jj, 1/r_jj and q_j, written
     // to LDS and to its place in A (which publishes it to the polling
     // workgroups), then, once every wave's stores have completed (an
@@ -469,51 +468,67 @@ __global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *ar
     };
     bool live = true;
     if (w == 0 && n > 0) live = publish(0);
+    // q_m for m <= k: in its owner's LDS slot, or received into staging slot
+    // m mod qslots
+    auto qcol = [&](int m) {
+        return m % G == w ? own(m / G) : planar(qs0 + (size_t)(m % qslots) * cst, N);
+    };
+    auto rstore = [&](int j, int k, const cx<R> &r) {
+        if (t == 0) cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * n + k) * W, r);
+    };
+    // q_k applied to own column slot c
+    auto apply1 = [&](const Col &qk, int k, int c) {
+        const Col aj = own(c);
+        const cx<R> r = col_dot<R>(qk, aj, N, t, ts);
+        rstore(w + c * G, k, r);
+        col_axpy<R>(qk, aj, r, N, t);
+    };
+    // q_k applied to own columns from slot c on, two at a time
+    auto apply_from = [&](const Col &qk, int k, int c) {
+        for (; c + 1 < mine; c += 2) {
+            cx<R> r0, r1;
+            col_update2<R>(qk, own(c), own(c + 1), N, t, ts, r0, r1);
+            rstore(w + c * G, k, r0);
+            rstore(w + (c + 1) * G, k, r1);
+        }
+        if (c < mine) apply1(qk, k, c);
+    };
+    // The lead is this workgroup's first column beyond k that is not the
+    // right-hand side.  While it is k+2 (with two staging slots), q_k goes
+    // to the lead alone and the other columns wait; once the lead is k+1 it
+    // takes q_k and is published first, then the other columns take every q
+    // they still lack, in order.  So the lead is ready for q_{k+1} as soon
+    // as it comes; every column still takes q_0, q_1, ... in order.
+    int tp = 0;  // columns other than the lead have q_0 .. q_{tp-1}
     for (int k = 0; k < n && live; ++k) {
-        Col qk;
-        if (k % G == w) {
-            qk = own(k / G);
-        } else {
+        const int next = k < w ? w : w + ((k - w) / G + 1) * G;  // first own column > k
+        if (k % G != w) {
             // q_k is needed only while this workgroup has a column beyond k
-            if (k >= w && w + ((k - w) / G + 1) * G > n) break;
-            // q_k into the staging column, each lane its own rows (read back
+            if (next > n) break;
+            // q_k into its staging slot, each lane its own rows (read back
             // only by the same lane); the workgroup goes on only if every
             // lane got its rows
-            const int next = k < w ? w : w + ((k - w) / G + 1) * G;  // first own column > k
             bool ok = true;
             if (next - k > PIPE_EAGER) ok = pipe_wait(flg + k, stop, spin_limit, &s_go);
-            if (ok) ok = pipe_fetch<R>(col_ptr(a, b, k), qs, N, t, stop, spin_limit);
+            if (ok) ok = pipe_fetch<R>(col_ptr(a, b, k), qs0 + (size_t)(k % qslots) * cst, N, t, stop, spin_limit);
             if (__syncthreads_or(!ok)) {
                 live = false;
                 break;
             }
-            qk = qs_col;
         }
-        // own columns j > k in increasing order: column k+1 (on the chain)
-        // first and alone, then the others two at a time
-        auto rstore = [&](int j, const cx<R> &r) {
-            if (t == 0) cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * n + k) * W, r);
-        };
-        int c = k < w ? 0 : (k - w) / G + 1;
-        if (c < mine && w + c * G == k + 1) {
-            const Col aj = own(c);
-            const cx<R> r = col_dot<R>(qk, aj, N, t, ts);
-            rstore(k + 1, r);
-            col_axpy<R>(qk, aj, r, N, t);
-            if (k + 1 < n) live = publish(c);
-            ++c;
-        }
-        for (; c + 1 < mine && live; c += 2) {
-            cx<R> r0, r1;
-            col_update2<R>(qk, own(c), own(c + 1), N, t, ts, r0, r1);
-            rstore(w + c * G, r0);
-            rstore(w + (c + 1) * G, r1);
-        }
-        if (c < mine && live) {
-            const Col aj = own(c);
-            const cx<R> r = col_dot<R>(qk, aj, N, t, ts);
-            rstore(w + c * G, r);
-            col_axpy<R>(qk, aj, r, N, t);
+        const Col qk = qcol(k);
+        const int c = k < w ? 0 : (k - w) / G + 1;  // slot of column next
+        if (c >= mine) continue;
+        if (next == k + 1 && next < n) {
+            apply1(qk, k, c);
+            live = publish(c);
+            for (int m = tp; m <= k && live; ++m) apply_from(qcol(m), m, c + 1);
+            tp = k + 1;
+        } else if (qslots > 1 && next == k + 2 && next < n) {
+            apply1(qk, k, c);
+        } else {
+            apply_from(qk, k, c);
+            tp = k + 1;
         }
     }
     // the projected right-hand side (column n) goes back to its place
@@ -591,8 +606,105 @@ __global__ void k_fig2_pre(MgsArgs a) {
     if (b < a.B) (void)fig2_decide(problem_of(a, b));
 }
 
+// Back substitution of mgs_backsub with y in LDS (ys: [ROWS BT][2P]
+// doubles) and the rows of R fetched BS_AHEAD steps ahead into registers,
+// for n <= ROWS * BT: lane t holds rows t, t + BT, ... of y and forms dx_k
+// when it holds row k, which it hands to the others through one of two LDS
+// slots (one barrier per step, ordering LDS only: a slot is written again
+// two steps later, after the barrier of the step in between).  A step has
+// no branch around its loads and updates (rows at or beyond k keep their
+// value by a select, loads of rows not needed read r_k0), so that the
+// fetches of the steps ahead stay in flight.  The same operations in the
+// same order as mgs_backsub, so the same bits; dx written to global memory
+// at the end.
+constexpr int BS_AHEAD = 4;
+
+template <class R, int ROWS>
+HCN_DEV void mgs_backsub_lds(const MgsProblem &p, double *ys) {
+    constexpr int P = limbs<R>::P;
+    constexpr int W = 2 * P;
+    __shared__ cx<R> s_x[2];
+    const int t = threadIdx.x;
+    const int n = p.n;
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int i = t + r * BT;
+        const cx<R> y = i < n ? cload<R>(p.R + ((size_t)n * n + i) * W) : czero<R>();
+        cstore(ys + (size_t)i * W, y);
+    }
+    // what step k reads from global memory, fetched ahead: r_ki for the
+    // lane's rows i < k (other rows read r_k0, unused) and 1/r_kk
+    struct Ahead {
+        cx<R> rk[ROWS];
+        R iv;
+    };
+    auto fetch = [&](int k, Ahead &f) {
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int i = t + r * BT;
+            f.rk[r] = cload<R>(p.R + ((size_t)k * n + (i < k ? i : 0)) * W);
+        }
+        rload(p.inv + (size_t)k * P, f.iv);
+    };
+    // one step: dx_k by its owner, then y_i -= r_ki dx_k for i < k
+    auto step = [&](int k, const Ahead &f) {
+        if (k % BT == t) {
+            const cx<R> x = cscale(f.iv, cload<R>(ys + (size_t)k * W));
+            cstore(ys + (size_t)k * W, x);
+            s_x[k & 1] = x;
+        }
+        lds_barrier();  // the fetches of the steps ahead stay in flight
+        const cx<R> xk = s_x[k & 1];
+#pragma unroll
+        for (int r = 0; r < ROWS; ++r) {
+            const int i = t + r * BT;
+            double *q = ys + (size_t)i * W;
+            const cx<R> y = cload<R>(q);
+            const cx<R> u = csub(y, cmul(f.rk[r], xk));
+            cstore(q, i < k ? u : y);
+        }
+    };
+    // buffer u serves the steps k with (n - 1 - k) % BS_AHEAD == u
+    Ahead fb[BS_AHEAD];
+#pragma unroll
+    for (int u = 0; u < BS_AHEAD; ++u) fetch(n - 1 - u >= 0 ? n - 1 - u : 0, fb[u]);
+    int k0 = n - 1;
+    for (; k0 >= BS_AHEAD - 1; k0 -= BS_AHEAD) {
+#pragma unroll
+        for (int u = 0; u < BS_AHEAD; ++u) {
+            const int k = k0 - u;
+            step(k, fb[u]);
+            fetch(k - BS_AHEAD >= 0 ? k - BS_AHEAD : 0, fb[u]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < BS_AHEAD - 1; ++u)
+        if (k0 - u >= 0) step(k0 - u, fb[u]);
+#pragma unroll
+    for (int r = 0; r < ROWS; ++r) {
+        const int i = t + r * BT;
+        if (i < n) cstore(p.dx + (size_t)i * W, cload<R>(ys + (size_t)i * W));
+    }
+    __syncthreads();
+}
+
+// rows per lane of the LDS back substitution for n unknowns (0: the plain
+// one), and its dynamic LDS: y padded to ROWS * BT rows, within the 64 KB a
+// launch gets without an attribute (with the kernel's own slots)
+template <class R>
+HCN_DEV __host__ inline int backsub_rows(int n) {
+    const int rows = (n + BT - 1) / BT;
+    const size_t b = (size_t)rows * BT * 2 * limbs<R>::P * sizeof(double);
+    return rows >= 1 && rows <= 4 && b <= 60 * 1024 ? rows : 0;
+}
+template <class R>
+HCN_DEV __host__ inline size_t backsub_lds_bytes(int n) {
+    return (size_t)backsub_rows<R>(n) * BT * 2 * limbs<R>::P * sizeof(double);
+}
+
 template <class R>
 __global__ __launch_bounds__(BT) void k_mgs_finish(MgsArgs a, const int *sing) {
+    extern __shared__ double ys[];  // y of the back substitution, when it fits
     const int b = blockIdx.x;
     if (!problem_live(a, b)) return;
     const MgsProblem p = problem_of(a, b);
@@ -612,7 +724,18 @@ __global__ __launch_bounds__(BT) void k_mgs_finish(MgsArgs a, const int *sing) {
         }
         return;
     }
-    mgs_epilogue<R>(p, sing[b] != 0);
+    if (sing[b] != 0) {
+        mgs_singular<R>(p);
+        return;
+    }
+    switch (backsub_rows<R>(p.n)) {
+        case 1: mgs_backsub_lds<R, 1>(p, ys); break;
+        case 2: mgs_backsub_lds<R, 2>(p, ys); break;
+        case 3: mgs_backsub_lds<R, 3>(p, ys); break;
+        case 4: mgs_backsub_lds<R, 4>(p, ys); break;
+        default: mgs_backsub<R>(p); break;
+    }
+    mgs_after_backsub<R>(p);
 }
 
 __global__ void k_zero_int(int *p, int count) {
@@ -628,7 +751,7 @@ __global__ void k_zero_int(int *p, int count) {
 constexpr size_t PIPE_MAX_DYN_LDS = 159 * 1024;
 
 template <class R>
-static int pipe_groups(const MgsArgs &a, size_t *lds_out) {
+static int pipe_groups(const MgsArgs &a, size_t *lds_out, int *qslots_out) {
     static int cus = 0;
     if (!cus) {
         int dev = 0;
@@ -639,22 +762,27 @@ static int pipe_groups(const MgsArgs &a, size_t *lds_out) {
     const size_t cst = (size_t)a.N * 2 * limbs<R>::P * sizeof(double);
     for (int G = std::min(cus, a.n + 1); G >= 1; G /= 2) {
         const int mine = a.n / G + 1;
-        const size_t lds = (size_t)(mine + 1) * cst;
-        // the LDS of a CU (160 KB) holds the dynamic part and the kernel's
-        // own few hundred bytes of reduction slots
-        if (lds > PIPE_MAX_DYN_LDS) return 0;
-        if (hipFuncSetAttribute((const void *)k_mgs_pipe<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)lds) != hipSuccess) {
-            (void)hipGetLastError();
-            return 0;
-        }
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mgs_pipe<R>, TEAM, lds) !=
-            hipSuccess)
-            return 0;
-        if ((long)per_cu * cus >= (long)G * a.B) {
-            *lds_out = lds;
-            return G;
+        // two staging columns where they fit (the lead column goes first),
+        // else one
+        for (int qslots = 2; qslots >= 1; --qslots) {
+            const size_t lds = (size_t)(mine + qslots) * cst;
+            // the LDS of a CU (160 KB) holds the dynamic part and the
+            // kernel's own few hundred bytes of reduction slots
+            if (lds > PIPE_MAX_DYN_LDS) continue;
+            if (hipFuncSetAttribute((const void *)k_mgs_pipe<R>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds) != hipSuccess) {
+                (void)hipGetLastError();
+                return 0;
+            }
+            int per_cu = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_mgs_pipe<R>, TEAM, lds) !=
+                hipSuccess)
+                return 0;
+            if ((long)per_cu * cus >= (long)G * a.B) {
+                *lds_out = lds;
+                *qslots_out = qslots;
+                return G;
+            }
         }
     }
     return 0;
@@ -674,7 +802,8 @@ static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s)
     int *arrived = ints + a.B + 1;
     int *flags = ints + 2 * a.B + 1;
     size_t pipe_lds = 0;
-    const int G = variant == 5 ? pipe_groups<R>(a, &pipe_lds) : 0;
+    int qslots = 1;
+    const int G = variant == 5 ? pipe_groups<R>(a, &pipe_lds, &qslots) : 0;
     if (variant == 5 && G == 0) variant = 2;
     const long nz = variant == 5 ? 2L * a.B + 1 + (long)a.B * (a.n + 1) : a.B;
     hipLaunchKernelGGL(k_zero_int, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, ints, (int)nz);
@@ -685,7 +814,7 @@ static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s)
         if (variant == 5) {
             MgsArgs av = a;
             long spin = g_wait_limit;
-            void *args[] = {&av, &sing, &arrived, &flags, &spin};
+            void *args[] = {&av, &sing, &arrived, &flags, &spin, &qslots};
             const hipError_t e = hipLaunchCooperativeKernel((const void *)k_mgs_pipe<R>, dim3(G, a.B),
                                                             dim3(TEAM), args, (unsigned)pipe_lds, s);
             // a launch the device cannot take whole goes right-looking
@@ -701,7 +830,7 @@ static int launch_big_t(const MgsArgs &a, int variant, int *ints, hipStream_t s)
             for (int k = 0; k < a.n; ++k)
                 hipLaunchKernelGGL(k_mgs_rl<R>, dim3(a.n - k, a.B), dim3(BT), 0, s, a, k, sing);
         }
-        hipLaunchKernelGGL(k_mgs_finish<R>, dim3(a.B), dim3(BT), 0, s, a, sing);
+        hipLaunchKernelGGL(k_mgs_finish<R>, dim3(a.B), dim3(BT), backsub_lds_bytes<R>(a.n), s, a, sing);
     }
     return (int)hipGetLastError();
 }

@@ -23,6 +23,15 @@ namespace hcn {
 
 constexpr int MGS_THREADS = 256;
 
+// A workgroup barrier that orders LDS accesses only: global loads and
+// stores still in flight stay in flight (a plain __syncthreads waits for
+// every one of them first)
+HCN_DEV void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // one problem with every pointer resolved
 struct MgsProblem {
     int N, n, mode, lds;
@@ -65,6 +74,21 @@ HCN_DEV double residual_norm(const MgsProblem &p) {
     double res = 0.0;
     for (int q = 0; q < p.nparts; ++q) res = nanmax(res, p.norm_part[q]);
     return res;
+}
+
+// residual_norm by every lane of the workgroup (MGS_THREADS lanes, all of
+// which call it), the same value on each: the maximum is exact and a NaN
+// anywhere gives NaN, so the grouping does not matter
+HCN_DEV double residual_norm_wg(const MgsProblem &p) {
+    __shared__ double s_rn[MGS_THREADS / 64];
+    double m = 0.0;
+    for (int q = threadIdx.x; q < p.nparts; q += MGS_THREADS) m = nanmax(m, p.norm_part[q]);
+    for (int off = 32; off >= 1; off >>= 1) m = nanmax(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) s_rn[threadIdx.x >> 6] = m;
+    __syncthreads();
+    double r = s_rn[0];
+    for (int w = 1; w < MGS_THREADS / 64; ++w) r = nanmax(r, s_rn[w]);
+    return r;
 }
 
 // Fig. 2 before the solve: fail if the residual grew beyond the previous one
@@ -111,27 +135,16 @@ HCN_DEV void fig2_after_update(PathState &st, double dxn) {
     }
 }
 
+// The epilogue's two parts, after a solve that found no singular column.
+// Back substitution R dx = y in place in dx (it starts as y = column n of
+// R): for k = n-1 down to 0, dx_k = y_k / r_kk (times the stored 1/r_kk),
+// then y_i -= r_ik dx_k for every i < k.
 template <class R>
-HCN_DEV void mgs_epilogue(const MgsProblem &p, bool singular) {
+HCN_DEV void mgs_backsub(const MgsProblem &p) {
     constexpr int P = limbs<R>::P;
     constexpr int W = 2 * P;
     const int tid = threadIdx.x;
     const int n = p.n;
-    if (singular) {
-        if (tid == 0) {
-            if (p.status) *p.status = HCN_ESINGULAR;
-            if (p.mode == MGS_NEWTON_FIG2 || p.mode == MGS_MIXED_SOLVE) {
-                p.st->c_status = HCN_ESINGULAR;
-                p.st->c_active = 0;
-            }
-            if (p.mode == MGS_NEWTON_STEP && p.norms) {
-                p.norms[0] = residual_norm(p);
-                p.norms[1] = __builtin_nan("");
-            }
-        }
-        return;
-    }
-    // back substitution, in place in dx (starts as y = column n of R)
     for (int i = tid; i < n; i += MGS_THREADS)
         cstore(p.dx + (size_t)i * W, cload<R>(p.R + ((size_t)n * n + i) * W));
     __syncthreads();
@@ -149,11 +162,21 @@ HCN_DEV void mgs_epilogue(const MgsProblem &p, bool singular) {
         }
         __syncthreads();
     }
+}
+
+// Then the status of a plain solve, or for Newton the update norm, the NaN
+// check, x += dx and the Fig. 2 bookkeeping (dx complete in global memory,
+// the workgroup synchronised).
+template <class R>
+HCN_DEV void mgs_after_backsub(const MgsProblem &p) {
+    constexpr int P = limbs<R>::P;
+    constexpr int W = 2 * P;
+    const int tid = threadIdx.x;
+    const int n = p.n;
     if (p.mode == MGS_SOLVE || p.mode == MGS_MIXED_SOLVE) {
         if (tid == 0 && p.status) *p.status = HCN_OK;
         return;
     }
-    // Newton: update norm, NaN check, x += dx
     __shared__ double s_red[MGS_THREADS / 64];
     double m = 0.0;
     for (int i = tid; i < n; i += MGS_THREADS) m = nanmax(m, clead_abs(cload<R>(p.dx + (size_t)i * W)));
@@ -169,10 +192,11 @@ HCN_DEV void mgs_epilogue(const MgsProblem &p, bool singular) {
             cstore(q, cadd(cload<R>(q), cload<R>(p.dx + (size_t)i * W)));
         }
     }
+    const double res = p.mode == MGS_NEWTON_STEP && p.norms ? residual_norm_wg(p) : 0.0;
     if (tid == 0) {
         if (p.mode == MGS_NEWTON_STEP) {
             if (p.norms) {
-                p.norms[0] = residual_norm(p);
+                p.norms[0] = res;
                 p.norms[1] = dxn;
             }
             if (p.status) *p.status = isnan_dx ? HCN_NAN : HCN_OK;
@@ -180,6 +204,32 @@ HCN_DEV void mgs_epilogue(const MgsProblem &p, bool singular) {
             fig2_after_update(*p.st, dxn);
         }
     }
+}
+
+// a singular column: the problem's status, and for Newton its norms
+template <class R>
+HCN_DEV void mgs_singular(const MgsProblem &p) {
+    if (threadIdx.x == 0) {
+        if (p.status) *p.status = HCN_ESINGULAR;
+        if (p.mode == MGS_NEWTON_FIG2 || p.mode == MGS_MIXED_SOLVE) {
+            p.st->c_status = HCN_ESINGULAR;
+            p.st->c_active = 0;
+        }
+        if (p.mode == MGS_NEWTON_STEP && p.norms) {
+            p.norms[0] = residual_norm(p);
+            p.norms[1] = __builtin_nan("");
+        }
+    }
+}
+
+template <class R>
+HCN_DEV void mgs_epilogue(const MgsProblem &p, bool singular) {
+    if (singular) {
+        mgs_singular<R>(p);
+        return;
+    }
+    mgs_backsub<R>(p);
+    mgs_after_backsub<R>(p);
 }
 
 // The partner's value at butterfly level M (lanes l and l ^ M).  Inside a
