@@ -224,6 +224,22 @@ HCN_DEV R col_norm2(const Col &a, int N, int t, TeamSums<R> &ts, bool act = true
     return team_rsum(acc, t, ts.r, ts.pr);
 }
 
+// a -= r q, returning the lane's part of ||a||^2 over the updated rows, in
+// col_norm2's order (team_rsum of it gives col_norm2's bits)
+template <class R>
+HCN_DEV R col_axpy_norm2(const Col &q, const Col &a, const cx<R> &r, int N, int t) {
+    R acc = rmake<R>(0.0);
+    bool first = true;
+    for (int i = t; i < N; i += TEAM) {
+        const cx<R> u = csub(col_ld<R>(a, i), cmul(r, col_ld<R>(q, i)));
+        col_st<R>(a, i, u);
+        const R v = cnorm2(u);
+        acc = first ? v : add(acc, v);
+        first = false;
+    }
+    return acc;
+}
+
 // Loads and stores coherent across the device (agent-scope atomics: they
 // reach the memory side, past the per-XCD L2), for columns handed from one
 // workgroup to another inside a launch
@@ -275,11 +291,11 @@ HCN_DEV bool col_pivot(const MgsArgs &a, int b, int j, const R &s, int t, R *iv_
 // r_jj, 1/r_jj and q_j = a_j / r_jj on the column at `aj` by the one-team
 // workgroup; false (on every lane) for a singular column
 template <class R>
-HCN_DEV bool col_normalise(const MgsArgs &a, int b, int j, double *aj, TeamSums<R> &ts) {
+HCN_DEV bool col_normalise(const MgsArgs &a, int b, int j, double *aj, const R &s2) {
     const int t = threadIdx.x;
     const Col c = interleaved<R>(aj);
     R iv;
-    if (!col_pivot<R>(a, b, j, col_norm2<R>(c, a.N, t, ts), t, &iv)) return false;
+    if (!col_pivot<R>(a, b, j, s2, t, &iv)) return false;
     col_scale<R>(c, iv, a.N, t);
     return true;
 }
@@ -308,16 +324,23 @@ __global__ __launch_bounds__(BT) void k_mgs_rl(MgsArgs a, int k, int *sing) {
     const int j = (k < 0) ? 0 : k + 1 + (int)blockIdx.x;
     if (j > a.n) return;
     double *aj = col_ptr(a, b, j);
+    const Col c = interleaved<R>(aj);
+    const bool next = j == k + 1 && j < a.n;
+    R part = rmake<R>(0.0);  // the lane's part of the squared norm of column k+1
     if (k >= 0) {
         const double *qk = col_ptr(a, b, k);
-        const Col q = interleaved<R>((double *)qk), c = interleaved<R>(aj);
+        const Col q = interleaved<R>((double *)qk);
         const cx<R> r = col_dot<R>(q, c, a.N, threadIdx.x, ts);
         if (threadIdx.x == 0)
             cstore(a.R + (size_t)b * a.R_pstride + ((size_t)j * a.n + k) * W, r);
-        col_axpy<R>(q, c, r, a.N, threadIdx.x);
+        if (next)
+            part = col_axpy_norm2<R>(q, c, r, a.N, threadIdx.x);
+        else
+            col_axpy<R>(q, c, r, a.N, threadIdx.x);
     }
-    if (j == k + 1 && j < a.n) {
-        if (!col_normalise<R>(a, b, j, aj, ts) && threadIdx.x == 0) sing[b] = 1;
+    if (next) {
+        const R s2 = k >= 0 ? team_rsum(part, (int)threadIdx.x, ts.r, ts.pr) : col_norm2<R>(c, a.N, threadIdx.x, ts);
+        if (!col_normalise<R>(a, b, j, aj, s2) && threadIdx.x == 0) sing[b] = 1;
     }
 }
 
@@ -452,11 +475,12 @@ __global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *ar
     // workgroups), then, once every wave's stores have completed (an
     // agent-scope release; a workgroup barrier alone does not wait for
     // global stores), its flag.  False: singular.
-    auto publish = [&](int c) -> bool {
+    auto publish = [&](int c, const R *part) -> bool {
         const int j = w + c * G;
         const Col aj = own(c);
         R iv;
-        if (!col_pivot<R>(a, b, j, col_norm2<R>(aj, N, t, ts), t, &iv)) {
+        const R s2 = part ? team_rsum(*part, t, ts.r, ts.pr) : col_norm2<R>(aj, N, t, ts);
+        if (!col_pivot<R>(a, b, j, s2, t, &iv)) {
             if (t == 0) __hip_atomic_store(stop, PIPE_SINGULAR, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
         }
@@ -467,7 +491,7 @@ __global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *ar
         return true;
     };
     bool live = true;
-    if (w == 0 && n > 0) live = publish(0);
+    if (w == 0 && n > 0) live = publish(0, nullptr);
     // q_m for m <= k: in its owner's LDS slot, or received into staging slot
     // m mod qslots
     auto qcol = [&](int m) {
@@ -520,8 +544,12 @@ __global__ __launch_bounds__(TEAM) void k_mgs_pipe(MgsArgs a, int *sing, int *ar
         const int c = k < w ? 0 : (k - w) / G + 1;  // slot of column next
         if (c >= mine) continue;
         if (next == k + 1 && next < n) {
-            apply1(qk, k, c);
-            live = publish(c);
+            // the lead: its update forms its squared norm on the way
+            const Col aj = own(c);
+            const cx<R> r = col_dot<R>(qk, aj, N, t, ts);
+            rstore(next, k, r);
+            const R part = col_axpy_norm2<R>(qk, aj, r, N, t);
+            live = publish(c, &part);
             for (int m = tp; m <= k && live; ++m) apply_from(qcol(m), m, c + 1);
             tp = k + 1;
         } else if (qslots > 1 && next == k + 2 && next < n) {
