@@ -64,18 +64,18 @@ HBM_PEAK_GBS = 8000.0
 # COUNTERS_DIGEST[kernel] (source_digest(kernel), over KERNEL_SOURCES[kernel]);
 # other sources report traffic null.
 HBM_COUNTERS_KIB = {
-    "mgs": {(8, 0): (918147.4, 5360362.0), (8, 1): (274855.4, 205534.4), (8, 2): (274997.8, 206143.1),
-            (8, 3): (437179.1, 542292.4), (16, 0): (893944.9, 4636952.2), (16, 1): (274880.6, 205976.1),
-            (16, 2): (275024.1, 205808.5), (16, 3): (453015.0, 540628.5), (32, 0): (798519.7, 3995524.2),
-            (32, 1): (274889.4, 207216.3), (32, 3): (481071.6, 537031.1)},
-    "eval_monomials": (38501.1, 5570560.0), "eval_sums": (3652239.9, 393933.1)}
+    "mgs": {(8, 0): (940205.8, 5431379.5), (8, 1): (274867.8, 205521.7), (8, 2): (275007.4, 206103.8),
+            (8, 3): (437361.6, 542741.0), (16, 0): (902185.8, 4659451.0), (16, 1): (274886.3, 205974.5),
+            (16, 2): (275026.6, 205790.0), (16, 3): (448043.9, 540755.6), (32, 0): (800438.8, 3981592.1),
+            (32, 1): (274887.6, 207732.5), (32, 3): (480435.0, 537156.0)},
+    "eval_monomials": (38119.7, 5570560.0), "eval_sums": (3652598.2, 393928.7)}
 KERNEL_SOURCES = {
     "mgs": ("mgs.hip", "mgs_common.hpp", "mp.hpp", "internal.hpp", "tune.hip"),
     "eval_monomials": ("eval.hip", "eval_body.hpp", "mp.hpp", "internal.hpp"),
     "eval_sums": ("eval.hip", "eval_body.hpp", "mp.hpp", "internal.hpp"),
 }
-COUNTERS_DIGEST = {"mgs": "098b5eda59229865", "eval_monomials": "28832b224f059a8e",
-                   "eval_sums": "28832b224f059a8e"}
+COUNTERS_DIGEST = {"mgs": "dffa30eddf61b91e", "eval_monomials": "07817b10382072ec",
+                   "eval_sums": "07817b10382072ec"}
 MGS_PIN = None  # (lane group, storage) from --mgs-group / --mgs-storage, else autotuned
 FETCH_CAL, WRITE_CAL = 10485760 / (5131.5 * 1024), 1.0
 _T0 = time.time()
