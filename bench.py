@@ -14,7 +14,8 @@ Reported beside it, one object per workload:
 * qd: the same in quad-double (2048 points);
 * single: one Newton step of one point (latency);
 * track8: single paths of random n = 8 systems tracked from t = 0 to 1
-  (100 systems; status, steps, latency and paths/s);
+  (100 systems; status, steps, latency and paths/s), and of their
+  finite-roots variants (every path ends at a finite root);
 * sparse512: one Newton step of the sparse n = 512 system per MGS variant,
   with the bitwise comparison of the variants;
 * batch64: 4096 paths of 64 random systems in one slot-table batch (Newton
@@ -236,6 +237,36 @@ def track8_leg(hcn, S, dev, seeds: int = 100, mode_seeds: int = 8) -> dict:
                   "ms_per_path_median": float(np.median([d for d, _ in per[m]]) * 1e3),
                   "us_per_step": float(sum(d for d, _ in per[m]) / max(sum(k for _, k in per[m]), 1) * 1e6)}
     res["sample"] = sample
+    # the finite-roots variant of the same systems (each equation gains a
+    # pure power of its degree and a constant term, so no path goes to
+    # infinity): the tracker with the degree-4 predictor, one path at a time
+    progress("track8: finite-roots systems")
+    fsample, fms = [], []
+    for seed in range(seeds):
+        ps = S.with_finite_roots(S.small_track_system(seed, 2), seed)
+        sd = hcn.System(ps)
+        gam = S.random_unit_gamma(S.rng_for(0, 100 + seed), 2)
+        x0 = torch.from_numpy(S.ones_point(ps.n, 2)).to(dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xo, r = hcn.track_paths(sd, gam, x0[None], predictor_order=PLANTED_ORDER)
+        xh = xo[0].cpu().numpy()
+        fms.append((time.perf_counter() - t0) * 1e3)
+        r = r[0]
+        fsample.append({"seed": seed, "gamma": gam, "x0": S.ones_point(ps.n, 2), "x1": xh,
+                        "status": int(r["status"]), "steps": int(r["steps"]), "end_status": int(r["end_status"])})
+        sd.free()
+    fms = np.array(fms)
+    fok = sum(1 for q in fsample if q["status"] == 0)
+    res["finite_roots"] = {
+        "paths": seeds, "predictor_order": PLANTED_ORDER, "ok": fok, "success_rate": fok / seeds,
+        "ok_and_refined_to_1e-28": int(sum(1 for q in fsample if q["status"] == 0 and q["end_status"] == 0)),
+        "status": status_hist([q["status"] for q in fsample]),
+        "steps_median": float(np.median([q["steps"] for q in fsample])),
+        "paths_per_s": seeds / (fms.sum() / 1e3),
+        "p50_ms": float(np.percentile(fms, 50)), "p99_ms": float(np.percentile(fms, 99)),
+        "us_per_step": float(fms.sum() * 1e3 / max(sum(q["steps"] for q in fsample), 1))}
+    res["sample_finite"] = fsample
     return res
 
 
@@ -919,16 +950,17 @@ def sparse_errors(O, ps, x0, x1s: dict) -> dict:
     return out
 
 
-def track_errors(O, items, threads: int) -> dict:
-    """Oracle tracking of the same paths (one thread per path): status and
-    step count against the GPU's, end points against each other, and the
-    quad-double residual of the GPU end point."""
+def track_errors(O, items, threads: int, **track_kw) -> dict:
+    """Oracle tracking of the same paths (one thread per path, with the
+    GPU's tracking parameters track_kw): status and step count against the
+    GPU's, end points against each other, and the quad-double residual of
+    the GPU end point."""
     import numpy as np
 
     def one(it):
         ps, gam, x0, x1 = it["ps"], it["gamma"], it["x0"], it["x1"]
         t0 = time.perf_counter()
-        xo, r = O.track(ps, O.total_degree_start(ps), gam, 1, x0)
+        xo, r = O.track(ps, O.total_degree_start(ps), gam, 1, x0, **track_kw)
         ms = (time.perf_counter() - t0) * 1e3
         same = (r.status == it["status"] and r.steps == it["steps"])
         both_ok = r.status == 0 and it["status"] == 0
@@ -1032,6 +1064,11 @@ def cpu_baseline(gpu: dict, target_s: float = 15.0):
         progress("oracle errors: tracked n = 8 paths")
         items = [dict(s, ps=S.small_track_system(s["seed"], 2)) for s in gpu["track8"]["sample"]]
         errs["track8"] = track_errors(O, items, threads)
+        if gpu["track8"].get("sample_finite"):
+            progress("oracle errors: tracked n = 8 paths, finite-roots systems")
+            items = [dict(q, ps=S.with_finite_roots(S.small_track_system(q["seed"], 2), q["seed"]))
+                     for q in gpu["track8"]["sample_finite"][:32]]
+            errs["track8_finite"] = track_errors(O, items, threads, predictor_order=PLANTED_ORDER)
     if gpu.get("sparse512"):
         progress("oracle errors: sparse n = 512")
         smp = gpu["sparse512"]["sample"]
@@ -1113,12 +1150,14 @@ def main() -> int:
     def strip(leg):
         if leg is None:
             return None
-        return {k: v for k, v in leg.items() if k != "sample"}
+        return {k: v for k, v in leg.items() if not k.startswith("sample")}
 
     def with_err(leg, key):
         d = strip(leg)
         if d is not None and key in errs:
             d["oracle"] = errs[key]
+        if d is not None and key == "track8" and "finite_roots" in d and "track8_finite" in errs:
+            d["finite_roots"]["oracle"] = errs["track8_finite"]
         return d
 
     line = {
