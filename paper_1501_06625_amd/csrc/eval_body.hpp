@@ -200,11 +200,18 @@ HCN_DEV void mon_one(const SysView &s, int m, const PointView &pv, double *out) 
 // mon_one for monomials of any size (more variables than the unrolled forms
 // cover): the same operations in the same order as mon_one with MON_FSLOT
 // (or MON_VALUES), with loops over the monomial's own k, so the bits are
-// those of mon_one; forward products parked in the output slots.
+// those of mon_one; forward products parked in the output slots.  The loops
+// take LONG_AHEAD positions at a time and issue their loads (positions,
+// exponents, variables, parked products) before the products that use
+// them, so that a lane waits for memory once per group, not once per
+// position.
+constexpr int LONG_AHEAD = 4;
+
 template <class R, int MODE, bool UNI = false>
 HCN_DEV void mon_one_long(const SysView &s, int m, const PointView &pv, double *out) {
     static_assert(MODE != MON_FREG, "the long form parks its forward products in the slots");
     constexpr int W = 2 * limbs<R>::P;
+    constexpr int U = LONG_AHEAD;
     const int k = s.mon_k[m];
     const int slot = s.mon_slot[m];
     const int stride = s.mon_stride[m];
@@ -219,26 +226,43 @@ HCN_DEV void mon_one_long(const SysView &s, int m, const PointView &pv, double *
     };
     cx<R> Flast = czero<R>(), ylast = czero<R>(), pc = czero<R>();
     bool has_pc = false;
-    for (int p = 0; p < k; ++p) {
-        int v;
-        const cx<R> y = load_y<R>(s, pv, p, m, v);
-        const int e = s.ex[(size_t)p * s.nmon + m];
-        if constexpr (UNI) {
-            cx<R> pw = y;
-            if (e >= 3) pw = cload<R>(pv.pows + ((size_t)(e - 3) * s.n + v) * W);
-            if (e == 1) pw = cone<R>();
-            pc = (p == 0) ? pw : cmul(pc, pw);
-        } else if (e >= 2) {
-            const cx<R> pw = cpow_small(y, e - 1);
-            pc = has_pc ? cmul(pc, pw) : pw;
-            has_pc = true;
+    for (int p0 = 0; p0 < k; p0 += U) {
+        cx<R> yb[U];
+        int vb[U], eb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 + u;
+            vb[u] = 0;
+            eb[u] = 1;
+            yb[u] = czero<R>();
+            if (p < k) {
+                yb[u] = load_y<R>(s, pv, p, m, vb[u]);
+                eb[u] = s.ex[(size_t)p * s.nmon + m];
+            }
         }
-        if (p <= k - 2) {
-            const cx<R> Fp = (p == 0) ? y : cmul(Flast, y);
-            if (MODE == MON_FSLOT) cstore(out + (size_t)(slot + (p + 2) * stride) * W, Fp);
-            Flast = Fp;
-        } else {
-            ylast = y;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 + u;
+            if (p >= k) break;
+            const cx<R> y = yb[u];
+            const int v = vb[u], e = eb[u];
+            if constexpr (UNI) {
+                cx<R> pw = y;
+                if (e >= 3) pw = cload<R>(pv.pows + ((size_t)(e - 3) * s.n + v) * W);
+                if (e == 1) pw = cone<R>();
+                pc = (p == 0) ? pw : cmul(pc, pw);
+            } else if (e >= 2) {
+                const cx<R> pw = cpow_small(y, e - 1);
+                pc = has_pc ? cmul(pc, pw) : pw;
+                has_pc = true;
+            }
+            if (p <= k - 2) {
+                const cx<R> Fp = (p == 0) ? y : cmul(Flast, y);
+                if (MODE == MON_FSLOT) cstore(out + (size_t)(slot + (p + 2) * stride) * W, Fp);
+                Flast = Fp;
+            } else {
+                ylast = y;
+            }
         }
     }
     const cx<R> cp = UNI ? cmul(c, pc) : (has_pc ? cmul(c, pc) : c);
@@ -252,12 +276,31 @@ HCN_DEV void mon_one_long(const SysView &s, int m, const PointView &pv, double *
     if (MODE == MON_VALUES) return;
     cstore(out + (size_t)(slot + k * stride) * W,
            escale(cmul(cp, Flast), s.ex[(size_t)(k - 1) * s.nmon + m]));
-    for (int p = k - 2; p >= 1; --p) {
-        const cx<R> Fpm1 = cload<R>(out + (size_t)(slot + (p + 1) * stride) * W);
-        cstore(out + (size_t)(slot + (p + 1) * stride) * W,
-               escale(cmul(Fpm1, Bk), s.ex[(size_t)p * s.nmon + m]));
-        int v;
-        Bk = cmul(Bk, load_y<R>(s, pv, p, m, v));
+    // positions k-2 down to 1; position p reads F_{p-1} from slot p+1 and
+    // writes its partial there (each slot read, then written, by the same
+    // position)
+    for (int p0 = k - 2; p0 >= 1; p0 -= U) {
+        cx<R> Fb[U], yb[U];
+        int eb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 - u;
+            eb[u] = 1;
+            Fb[u] = yb[u] = czero<R>();
+            if (p >= 1) {
+                Fb[u] = cload<R>(out + (size_t)(slot + (p + 1) * stride) * W);
+                eb[u] = s.ex[(size_t)p * s.nmon + m];
+                int v;
+                yb[u] = load_y<R>(s, pv, p, m, v);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = p0 - u;
+            if (p < 1) break;
+            cstore(out + (size_t)(slot + (p + 1) * stride) * W, escale(cmul(Fb[u], Bk), eb[u]));
+            Bk = cmul(Bk, yb[u]);
+        }
     }
     cstore(out + (size_t)(slot + stride) * W, escale(Bk, s.ex[m]));
 }

@@ -6,7 +6,8 @@ through the C ABI:
   at n = 128 and 352 (monomials of up to 352 variables, the loop form of
   the reverse mode): the closed-form root gives f = 0 to rounding, Euler's
   identity holds for the homogeneous equations, and the Jacobian rows of
-  sampled equations equal the oracle's (a one-equation system each);
+  sampled equations equal the oracle's (a one-equation system each); the
+  loop form gives the bits of the unrolled forms;
 * minor expansions (Section 4.1): against the oracle;
 * complex double (the third mode of Section 3.1): arithmetic bit for bit,
   evaluation, MGS and Newton against the oracle in double;
@@ -121,6 +122,39 @@ def test_cyclic_large_properties(H, n):
         e = np.abs(limb_diff(J[1][:, i], Jo[:, 0])) / np.maximum(SJ[:, i], 1e-300)
         assert e.max() <= GATE[P], (i, e.max())
         assert abs(limb_diff(f[1][i], fo[0])) / Sf[i] <= GATE[P]
+
+
+@pytest.mark.parametrize("P", [2, 4])
+def test_long_form_bitwise(H, P):
+    """A monomial of more than 64 variables sends every monomial of its
+    system to the loop form of the reverse mode (loads issued a group of
+    positions ahead).  A random system with such a monomial added to its
+    last equation gives, in every other equation, the bits of f and J of the
+    system without it, whose monomials take the unrolled forms (exponents up
+    to 3: the staged powers of the uniform form; DD keeps its forward
+    products in registers, QD in the slots)."""
+    n = 70
+    rng = np.random.default_rng(31 + P)
+    A = S.random_system(rng, n, n, (2, 6), (1, 8), (1, 2, 3), P=P)
+    lv = np.sort(rng.choice(n, size=66, replace=False)).astype(np.int32)
+    le = rng.choice([1, 2, 3], size=66).astype(np.int32)
+    coef = S.unit_complex(rng.uniform(0.0, 6.283, size=1), P).reshape(1, 2, P)
+    B = S.PolySystem(N=n, n=n, P=P,
+                     eq_ptr=np.concatenate([A.eq_ptr[:-1], [A.eq_ptr[-1] + 1]]).astype(np.int32),
+                     mon_ptr=np.concatenate([A.mon_ptr, [A.mon_ptr[-1] + 66]]).astype(np.int32),
+                     var=np.concatenate([A.var, lv]).astype(np.int32),
+                     exp=np.concatenate([A.exp, le]).astype(np.int32),
+                     coef=np.concatenate([A.coef, coef]))
+    sa, sb = H.System(A), H.System(B)
+    assert sa.info().max_k <= 8 and sb.info().max_k == 66
+    x = np.stack([S.random_unit_point(S.rng_for(4, 700 + q), n, P) for q in range(3)])
+    fa, Ja = H.eval_jac(sa, dev(x))
+    fb, Jb = H.eval_jac(sb, dev(x))
+    fa, Ja, fb, Jb = (np.asarray(v.cpu().numpy()) for v in (fa, Ja, fb, Jb))
+    assert np.array_equal(fa[:, :n - 1].view(np.uint64), fb[:, :n - 1].view(np.uint64))
+    assert np.array_equal(Ja[:, :, :n - 1].view(np.uint64), Jb[:, :, :n - 1].view(np.uint64))
+    sa.free()
+    sb.free()
 
 
 # ---------------------------------------------------------------------------
