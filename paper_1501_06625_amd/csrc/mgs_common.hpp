@@ -260,14 +260,19 @@ HCN_DEV qd xshfl(const qd &v) {
 }
 
 // sum over the GRP consecutive lanes of a group (levels M, 2M, ... < GRP),
-// lower lane first, so every lane of the group holds the same bits
+// lower lane first in QD, so every lane of the group holds the same bits
+// (in FP64 and DD the order does not matter: the error-free sums of an
+// addition give the same pair whichever operand comes first)
 template <class R, int GRP, int M = 1>
 HCN_DEV R group_sum(R v, int lane) {
     if constexpr (M >= GRP) {
         return v;
     } else {
         const R o = xshfl<M>(v);
-        v = (lane & M) ? add(o, v) : add(v, o);
+        if constexpr (limbs<R>::P == 4)
+            v = (lane & M) ? add(o, v) : add(v, o);
+        else
+            v = add(v, o);  // add(v, o) and add(o, v) have the same bits in FP64 and DD
         return group_sum<R, GRP, 2 * M>(v, lane);
     }
 }
@@ -278,7 +283,10 @@ HCN_DEV cx<R> group_csum(cx<R> v, int lane) {
         return v;
     } else {
         const cx<R> o{xshfl<M>(v.re), xshfl<M>(v.im)};
-        v = (lane & M) ? cadd(o, v) : cadd(v, o);
+        if constexpr (limbs<R>::P == 4)
+            v = (lane & M) ? cadd(o, v) : cadd(v, o);
+        else
+            v = cadd(v, o);
         return group_csum<R, GRP, 2 * M>(v, lane);
     }
 }

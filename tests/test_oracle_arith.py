@@ -108,6 +108,30 @@ def test_sum_under_cancellation(P):
     assert _max_rel(P, a, b, r, "add") <= BOUND[P]["add"]
 
 
+def test_double_double_add_commutes_bitwise():
+    """The double-double sum does not depend on the order of its operands,
+    bit for bit (each of its error-free sums yields the same pair either
+    way), also under cancellation, with signed zeros and with exact sums:
+    the GPU's butterfly reductions in FP64 and DD rely on it to skip the
+    lane-order select."""
+    rng = np.random.default_rng(12)
+    a = _rand_numbers(rng, 2, 400)
+    b = _rand_numbers(rng, 2, 400)
+    b[:100] = -a[:100]                       # exact cancellation
+    b[100:200, 0] = -a[100:200, 0]           # leading limbs cancel
+    a[200:220] = 0.0
+    b[210:230] = -0.0
+    b[230:260] = a[230:260] * 2.0 ** -30     # different magnitudes
+    for x, y in ((a, b), (b, a)):
+        r1 = O.elementwise("add", 2, x, y)
+        r2 = O.elementwise("add", 2, y, x)
+        assert np.array_equal(r1.view(np.uint64), r2.view(np.uint64))
+    # the plain double sum as well (the degenerate case P = 1)
+    r1 = O.elementwise("add", 1, a[:, :1], b[:, :1])
+    r2 = O.elementwise("add", 1, b[:, :1], a[:, :1])
+    assert np.array_equal(r1.view(np.uint64), r2.view(np.uint64))
+
+
 @pytest.mark.parametrize("P", [2, 4])
 def test_mul_d_and_sqrt(P):
     rng = np.random.default_rng(33 + P)
