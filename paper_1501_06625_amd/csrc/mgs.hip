@@ -9,11 +9,12 @@
 
 namespace hcn {
 
-template <class R, int GRP>
-__global__ __launch_bounds__(MGS_THREADS) void k_mgs(MgsArgs a, int lds) {
+// LDS: [A | b] staged in LDS (1) or left in global memory (0)
+template <class R, int GRP, int LDS>
+__global__ __launch_bounds__(MGS_THREADS) void k_mgs(MgsArgs a) {
     MgsProblem p = problem_of(a, blockIdx.x);
-    p.lds = lds;
-    mgs_wg<R, GRP>(p);
+    p.lds = LDS;
+    mgs_wg<R, GRP, LDS>(p);
 }
 
 template <class R, int GRP, int RPL, int CPG>
@@ -78,11 +79,13 @@ static void launch_grp(const MgsArgs &a, hipStream_t stream) {
     if (mode == 3 && launch_panel<R, GRP>(a, stream)) return;
     const size_t bytes = mgs_lds_bytes(a.N, a.n, limbs<R>::P);
     const int lds = (bytes <= mgs_lds_limit() && mode == 1) ? 1 : 0;
-    if (lds)
-        (void)hipFuncSetAttribute((const void *)k_mgs<R, GRP>,
+    if (lds) {
+        (void)hipFuncSetAttribute((const void *)k_mgs<R, GRP, 1>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    hipLaunchKernelGGL((k_mgs<R, GRP>), dim3(a.B), dim3(MGS_THREADS), lds ? bytes : 0, stream, a,
-                       lds);
+        hipLaunchKernelGGL((k_mgs<R, GRP, 1>), dim3(a.B), dim3(MGS_THREADS), bytes, stream, a);
+    } else {
+        hipLaunchKernelGGL((k_mgs<R, GRP, 0>), dim3(a.B), dim3(MGS_THREADS), 0, stream, a);
+    }
 }
 
 template <class R>

@@ -296,12 +296,16 @@ HCN_DEV __host__ inline size_t mgs_lds_bytes(int N, int n, int P) {
     return (size_t)(n + 1) * N * 2 * P * sizeof(double);
 }
 
-template <class R, int GRP>
+// STORE: where [A | b] lives, fixed at compile time (0 global memory, 1 LDS:
+// the loads and stores are then LDS or global instructions) or -1, p.lds at
+// run time (generic addressing)
+template <class R, int GRP, int STORE = -1>
 HCN_DEV void mgs_wg(const MgsProblem &p) {
     constexpr int P = limbs<R>::P;
     constexpr int W = 2 * P;
     constexpr int NGRP = MGS_THREADS / GRP;
     extern __shared__ double lds_cols[];
+    const bool in_lds = STORE < 0 ? p.lds != 0 : STORE == 1;
     __shared__ int s_flag;
     const int tid = threadIdx.x;
     const int g = tid / GRP;
@@ -315,7 +319,7 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
         if (s_flag) return;
     }
     const size_t cst = (size_t)N * W;
-    if (p.lds) {
+    if (in_lds) {
         for (size_t q = tid; q < (size_t)(n + 1) * cst; q += MGS_THREADS) {
             const int j = (int)(q / cst);
             const size_t off = q - (size_t)j * cst;
@@ -324,7 +328,9 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
         }
     }
     auto col = [&](int j) -> double * {
-        if (p.lds) return lds_cols + (size_t)j * cst;
+        if constexpr (STORE == 1) return lds_cols + (size_t)j * cst;
+        if constexpr (STORE == 0) return j < n ? p.A + (size_t)j * p.A_cstride : p.bcol;
+        if (in_lds) return lds_cols + (size_t)j * cst;
         return j < n ? p.A + (size_t)j * p.A_cstride : p.bcol;
     };
     // ||a_k||^2 over the rows of group 0, lower lane first
@@ -408,7 +414,7 @@ HCN_DEV void mgs_wg(const MgsProblem &p) {
         __syncthreads();
     }
     // a plain solve returns Q and the projected right-hand side in place
-    if (p.lds && p.mode == MGS_SOLVE && !singular) {
+    if (in_lds && p.mode == MGS_SOLVE && !singular) {
         for (size_t q = tid; q < (size_t)(n + 1) * cst; q += MGS_THREADS) {
             const int j = (int)(q / cst);
             const size_t off = q - (size_t)j * cst;
