@@ -65,18 +65,18 @@ HBM_PEAK_GBS = 8000.0
 # COUNTERS_DIGEST[kernel] (source_digest(kernel), over KERNEL_SOURCES[kernel]);
 # other sources report traffic null.
 HBM_COUNTERS_KIB = {
-    "mgs": {(8, 0): (940205.8, 5431379.5), (8, 1): (274867.8, 205521.7), (8, 2): (275007.4, 206103.8),
-            (8, 3): (437361.6, 542741.0), (16, 0): (902185.8, 4659451.0), (16, 1): (274886.3, 205974.5),
-            (16, 2): (275026.6, 205790.0), (16, 3): (448043.9, 540755.6), (32, 0): (800438.8, 3981592.1),
-            (32, 1): (274887.6, 207732.5), (32, 3): (480435.0, 537156.0)},
-    "eval_monomials": (38119.7, 5570560.0), "eval_sums": (3652598.2, 393928.7)}
+    "mgs": {(8, 0): (893249.1, 5304935.0), (8, 1): (274858.2, 205533.6), (8, 2): (274998.0, 205976.8),
+            (8, 3): (437413.0, 542423.9), (16, 0): (889280.4, 4627086.8), (16, 1): (274869.4, 205816.3),
+            (16, 2): (275004.8, 205733.9), (16, 3): (462631.3, 540749.1), (32, 0): (798724.1, 4027138.7),
+            (32, 1): (274879.8, 206869.0), (32, 3): (556396.1, 538210.7)},
+    "eval_monomials": (37741.6, 5570560.0), "eval_sums": (3653995.9, 393668.3)}
 KERNEL_SOURCES = {
     "mgs": ("mgs.hip", "mgs_common.hpp", "mp.hpp", "internal.hpp", "tune.hip"),
     "eval_monomials": ("eval.hip", "eval_body.hpp", "mp.hpp", "internal.hpp"),
     "eval_sums": ("eval.hip", "eval_body.hpp", "mp.hpp", "internal.hpp"),
 }
-COUNTERS_DIGEST = {"mgs": "dffa30eddf61b91e", "eval_monomials": "07817b10382072ec",
-                   "eval_sums": "07817b10382072ec"}
+COUNTERS_DIGEST = {"mgs": "628da6c22ca3657c", "eval_monomials": "eb84ed1d7708358a",
+                   "eval_sums": "eb84ed1d7708358a"}
 MGS_PIN = None  # (lane group, storage) from --mgs-group / --mgs-storage, else autotuned
 FETCH_CAL, WRITE_CAL = 10485760 / (5131.5 * 1024), 1.0
 _T0 = time.time()
