@@ -366,10 +366,72 @@ HCN_DEV long long ld_device_bits(const double *p) {
 // (planar), every word at every poll, until no word is empty.  Bounded:
 // false once the problem stopped (stop word set by another workgroup) or
 // the spin limit passed (the lane then sets the stop word to PIPE_TIMEOUT).
+// Two polls in flight, half a round trip apart, for up to FETCH_ROWS rows
+// per lane: the words are seen sooner after they land.
+constexpr int FETCH_ROWS = 2;
+
+template <class R>
+HCN_DEV bool pipe_fetch2(const double *src, double *qs, int N, int t, int *stop_word, long spin_limit) {
+    constexpr int W = 2 * limbs<R>::P;
+    // a poll: the lane's words and the stop word, loaded together
+    struct Poll {
+        long long w[FETCH_ROWS][W];
+        int stop;
+    };
+    Poll a, b;
+    // rows past N read row t again (their words are not used)
+    auto issue = [&](Poll &x) {
+#pragma unroll
+        for (int r = 0; r < FETCH_ROWS; ++r) {
+            const int i = t + r * TEAM < N ? t + r * TEAM : t;
+#pragma unroll
+            for (int l = 0; l < W; ++l) x.w[r][l] = ld_device_bits(src + (size_t)i * W + l);
+        }
+        x.stop = __hip_atomic_load(stop_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    };
+    // 1: complete (staged), 0: not yet, -1: give up
+    long spins = 0;
+    auto take = [&](const Poll &x) -> int {
+        bool all = true;
+#pragma unroll
+        for (int r = 0; r < FETCH_ROWS; ++r)
+#pragma unroll
+            for (int l = 0; l < W; ++l) all = all && x.w[r][l] != PIPE_EMPTY;
+        if (all) {
+#pragma unroll
+            for (int r = 0; r < FETCH_ROWS; ++r) {
+                const int i = t + r * TEAM;
+                if (i < N)
+#pragma unroll
+                    for (int l = 0; l < W; ++l) qs[(size_t)l * N + i] = __longlong_as_double(x.w[r][l]);
+            }
+            return 1;
+        }
+        if (x.stop != 0) return -1;
+        if (++spins > spin_limit) {
+            __hip_atomic_store(stop_word, PIPE_TIMEOUT, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return -1;
+        }
+        return 0;
+    };
+    issue(a);
+    for (;;) {
+        __builtin_amdgcn_s_sleep(8);
+        issue(b);
+        int r = take(a);
+        if (r != 0) return r > 0;
+        __builtin_amdgcn_s_sleep(8);
+        issue(a);
+        r = take(b);
+        if (r != 0) return r > 0;
+    }
+}
+
 template <class R>
 HCN_DEV bool pipe_fetch(const double *src, double *qs, int N, int t, int *stop_word, long spin_limit) {
     constexpr int W = 2 * limbs<R>::P;
     if (t >= N) return true;
+    if (N <= FETCH_ROWS * TEAM) return pipe_fetch2<R>(src, qs, N, t, stop_word, spin_limit);
     long spins = 0;
     for (;;) {
         bool all = true;
