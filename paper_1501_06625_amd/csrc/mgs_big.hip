@@ -9,8 +9,8 @@
 //
 // Right-looking: one launch per column step k; the workgroup of trailing
 // column j > k forms r_kj = q_k^H a_j and a_j -= r_kj q_k on global memory
-// (lane t sums rows t, t+256, ... in order; a 64-lane butterfly adding the
-// lower lane first; the four wavefront sums added in order); the workgroup
+// (lane t sums rows t, t+256, ... in order; a 64-lane butterfly; the four
+// wavefront sums added pairwise); the workgroup
 // of column k+1 then also normalises it (r_{k+1,k+1}, q_{k+1}).  The
 // trailing matrix is read and written once per step.
 //
@@ -56,13 +56,31 @@ constexpr int BT = MGS_THREADS;
 
 // Team operations on one column.  A team is 256 lanes (four wavefronts);
 // lane t of the team holds rows t, t + 256, ... .  A sum over the column is
-// lane t's rows in order, a 64-lane butterfly adding the lower lane first
-// (group_csum / group_sum: DPP moves within rows of 16 lanes, permutes
-// beyond), then the four wavefront sums in order, so every lane of the team
-// returns the same bits.  The right-looking workgroup is one team; the
+// lane t's rows in order, a 64-lane butterfly (group_csum / group_sum: DPP
+// moves within rows of 16 lanes, permutes beyond), then the four wavefront
+// sums added pairwise, so every lane of the team returns the same bits.  The right-looking workgroup is one team; the
 // pipelined workgroup is one team too.  `act` false: the lane adds no rows
 // (its part of the sum is zero) but keeps the barriers.
 constexpr int TEAM = MGS_THREADS;
+
+template <class T>
+HCN_DEV T sum2(const T &a, const T &b) { return add(a, b); }
+template <class R>
+HCN_DEV cx<R> sum2(const cx<R> &a, const cx<R> &b) { return cadd(a, b); }
+
+// The TEAM / 64 wavefront sums added pairwise, (w0 + w1) + (w2 + w3): two
+// dependent additions instead of three, the same order on every lane
+template <class T>
+HCN_DEV T wave_tree(const T *part) {
+    T v[TEAM / 64];
+#pragma unroll
+    for (int w = 0; w < TEAM / 64; ++w) v[w] = part[w];
+#pragma unroll
+    for (int h = 1; h < TEAM / 64; h <<= 1)
+#pragma unroll
+        for (int w = 0; w + h < TEAM / 64; w += 2 * h) v[w] = sum2(v[w], v[w + h]);
+    return v[0];
+}
 
 // The partial sums go through a ring of two slots, taken in turn (`ph`
 // flips at every call; every lane of the team makes the same calls): a slot
@@ -79,10 +97,7 @@ HCN_DEV cx<R> team_csum(cx<R> v, int t, cx<R> *ring, int &ph) {
     v = group_csum<R, 64>(v, lane);
     if (lane == 0) s_part[t >> 6] = v;
     lds_barrier();
-    cx<R> s = s_part[0];
-#pragma unroll
-    for (int w = 1; w < TEAM / 64; ++w) s = cadd(s, s_part[w]);
-    return s;
+    return wave_tree(s_part);
 }
 
 // two independent sums side by side, each in team_csum's order
@@ -98,14 +113,8 @@ HCN_DEV void team_csum2(cx<R> &v0, cx<R> &v1, int t, cx<R> *ring, int &ph) {
         s_part[TEAM / 64 + (t >> 6)] = v1;
     }
     lds_barrier();
-    cx<R> s0 = s_part[0], s1 = s_part[TEAM / 64];
-#pragma unroll
-    for (int w = 1; w < TEAM / 64; ++w) {
-        s0 = cadd(s0, s_part[w]);
-        s1 = cadd(s1, s_part[TEAM / 64 + w]);
-    }
-    v0 = s0;
-    v1 = s1;
+    v0 = wave_tree(s_part);
+    v1 = wave_tree(s_part + TEAM / 64);
 }
 
 template <class R>
@@ -116,10 +125,7 @@ HCN_DEV R team_rsum(R v, int t, R *ring, int &ph) {
     v = group_sum<R, 64>(v, lane);
     if (lane == 0) s_part[t >> 6] = v;
     lds_barrier();
-    R s = s_part[0];
-#pragma unroll
-    for (int w = 1; w < TEAM / 64; ++w) s = add(s, s_part[w]);
-    return s;
+    return wave_tree(s_part);
 }
 
 // the two rings of a team's sums (complex dot products, real squared norms)
