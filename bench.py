@@ -78,6 +78,12 @@ KERNEL_SOURCES = {
 COUNTERS_DIGEST = {"mgs": "628da6c22ca3657c", "eval_monomials": "eb84ed1d7708358a",
                    "eval_sums": "eb84ed1d7708358a"}
 MGS_PIN = None  # (lane group, storage) from --mgs-group / --mgs-storage, else autotuned
+TUNE_REPS = 20  # Newton steps per MGS configuration the autotuner times (--tune-reps)
+
+
+def set_tune_reps(reps: int) -> None:
+    global TUNE_REPS
+    TUNE_REPS = max(1, int(reps))
 FETCH_CAL, WRITE_CAL = 10485760 / (5131.5 * 1024), 1.0
 _T0 = time.time()
 STATUS_NAMES = {0: "ok", 1: "not_converged", 2: "diverged", 3: "max_steps", 4: "step_too_small",
@@ -148,7 +154,7 @@ def dense_leg(hcn, flops, S, dev, P: int, B: int, K: int, W: int, profile: bool,
         hcn.tune_set(P, ps.N, MGS_PIN[0], MGS_PIN[1])
         tuned = (MGS_PIN[0], MGS_PIN[1], None)
     else:
-        tuned = hcn.autotune(sysd, x0, reps=5) if B > 1 else None
+        tuned = hcn.autotune(sysd, x0, reps=TUNE_REPS) if B > 1 else None
     ws = hcn.newton_ws(sysd, B)
     for _ in range(W):
         x.copy_(x0)
@@ -1105,6 +1111,8 @@ def main() -> int:
     ap.add_argument("--sparse512-variants", default=None,
                     help="comma list of MGS variants for the sparse512 leg (" +
                          ", ".join(r[2] for r in SPARSE_RUNS) + "); default all")
+    ap.add_argument("--tune-reps", type=int, default=TUNE_REPS,
+                    help="Newton steps the autotuner times per MGS configuration of the dense legs")
     ap.add_argument("--batch-steps-only", action="store_true",
                     help="batch64: only the fixed-step timing (no paths to completion; for profiling)")
     args = ap.parse_args()
@@ -1114,6 +1122,7 @@ def main() -> int:
               file=sys.stderr)
         return 2
     global MGS_PIN
+    set_tune_reps(args.tune_reps)
     if args.mgs_group is not None:
         MGS_PIN = (args.mgs_group, args.mgs_storage)
     rank = int(os.environ.get("RANK", "0"))
