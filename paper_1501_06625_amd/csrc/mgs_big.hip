@@ -21,14 +21,17 @@
 // the places of its columns in A empty (a signalling-NaN pattern) and the
 // workgroups of a problem meet once.  The owner of column k normalises it
 // and publishes q_k in place in A (the column's final value) with
-// device-coherent stores: the data are their own flag, with no fence or
-// flag word on the chain.  Every workgroup takes q_k in order, each lane
-// polling its own rows until none is empty, and projects it out of its own
-// later columns, the next column first, so that the owner of column k+1 can
-// publish q_{k+1} while the others still work on q_k (look-ahead).  The
-// column operations are the right-looking variant's (same lanes, rows,
-// butterflies and order), so the results are bitwise the same; the trailing
-// matrix never leaves LDS and the step boundaries cost no launch.  Waits
+// device-coherent stores: for the workgroups next on the chain (whose next
+// column is k+1 or k+2) the data are their own flag, each lane polling its
+// own rows until none is empty, with no fence or flag word on the chain;
+// the others wait for a flag the owner raises once its stores are complete.
+// Every workgroup takes the q_k in order and projects each out of its own
+// later columns, its next column first (while that column is k+2 the
+// others wait), so that the owner of column k+1 can publish q_{k+1} while
+// the others still work on q_k (look-ahead).  The column operations are
+// the right-looking variant's (same lanes, rows, butterflies and order), so
+// the results are bitwise the same; the trailing matrix never leaves LDS
+// and the step boundaries cost no launch.  Waits
 // are bounded: a wait that times out (a workgroup not resident, which the
 // cooperative launch rules out) or a singular column stops every workgroup
 // of the problem, and the epilogue reports the problem as failed
